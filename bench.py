@@ -1,0 +1,139 @@
+#!/usr/bin/env python3
+"""Benchmark of the FWI hot path on one MI355X.
+
+A step is one complete forward modelling run of the 3-D workload (256^3 model
+grid, 24-cell sponge, 8th-order stencil, 2000 time steps, 256x256 receivers,
+seeded layered velocity), with every input already resident in HBM.  The
+line printed on stdout is JSON:
+
+    value      Gcell-updates/s over padded cells (cells x time steps / s)
+    roofline   the stencil step kernel against the HBM peak (16 algorithmic
+               bytes per cell-update: read p, p_prev, kappa; write p_next)
+    cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
+
+Only one GPU is used: --gpus above 1 exits with a message.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gcell-updates/s + %HBM roofline; gradient shots/s vs plain; p99 latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 16
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(P, nt_sample):
+    """The oracle as it stands, on the same model for nt_sample steps."""
+    import oracle
+    t0 = time.perf_counter()
+    oracle.forward(P.v, P.wavelet[:, :nt_sample], P.src_pos, P.rec_pos, P.dx, P.dt, P.order,
+                   P.nb, P.eta_max)
+    secs = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": P.padded_cells * nt_sample / secs / 1e9, "unit": "Gcell-updates/s",
+            "cores": cores, "kind": "oracle",
+            "sample": "fp64 oracle forward on the same 304^3 padded grid, %d of %d time steps "
+                      "(%.1f s, set-up included)" % (nt_sample, P.nt, secs)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=2000)
+    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU "
+              "sharding is a design note, not an implementation" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1912_08063_amd import api, workloads as wl
+
+    dev = torch.device("cuda:0")
+    log("generating workload")
+    P = wl.c2(nt=args.nt)
+    t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
+    v, w = t(P.v, torch.float32), t(P.wavelet, torch.float32)
+    s, r = t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
+    cfg = api.Config(dt=P.dt, dx=P.dx, order=P.order, nsponge=P.nb, eta_max=P.eta_max)
+    traces = torch.empty((P.nshots, P.nt, P.nrec), dtype=torch.float32, device=dev)
+    ws = api.Workspace()
+
+    def run():
+        api.forward(v, w, s, r, cfg, workspace=ws, out=traces)
+
+    for i in range(args.warmup):
+        run()
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(args.steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    log("timed %d steps: %.1f ms" % (args.steps, ms))
+    assert bool(torch.isfinite(traces).all()), "non-finite traces"
+
+    updates = P.padded_cells * P.nt * args.steps
+    value = updates / (ms * 1e-3) / 1e9
+    launches = P.nt * args.steps
+    avg_launch_s = ms * 1e-3 / launches
+    bytes_per_launch = BYTES_PER_UPDATE * P.padded_cells
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded layered velocity model, Ricker source",
+        "config": {
+            "workload": "3-D acoustic forward, 256^3 model + 24-cell sponge (304^3 padded), "
+                        "8th order, %d steps, 256x256 receivers" % P.nt,
+            "padded_cells": P.padded_cells, "model_cells": P.model_cells, "nt": P.nt,
+            "order": P.order, "parallelism": "single GPU",
+            "model_cell_updates_per_s": round(P.model_cells * P.nt * args.steps
+                                              / (ms * 1e-3) / 1e9, 3),
+        },
+        "roofline": {
+            "bound": "hbm", "kernel": "k_step3d<4,false> (stencil step, one launch per time step)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_us": round(avg_launch_s * 1e6, 2),
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, %d steps)" % args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * fwi.h -- C ABI of libfwi.so, the MI355X (gfx950) hot path of acoustic
+ * full-waveform inversion.
+ *
+ * Method (Huot et al., "High-resolution imaging on TPUs"):
+ *   Eq. 2  constant-density acoustic wave equation  P_tt = v^2 lap P + s;
+ *   Eq. 3  leapfrog  P^{n+1} = -P^{n-1} + 2P^n + v^2 dt^2 lap P^n + dt^2 s^n,
+ *          here with a sponge layer (damping 2 eta P_t, centred in time):
+ *            P^{n+1} = alpha (2P^n + kappa lap P^n + dt^2 s^n) - beta P^{n-1},
+ *            kappa = v^2 dt^2, alpha = 1/(1+eta dt), beta = (1-eta dt)/(1+eta dt);
+ *          eta = 0 on the whole model grid, so there the update is Eq. 3.
+ *   Fig. 3 / Section 3  central star Laplacian of order >= 8 (8th and 16th
+ *          order in Section 4); orders 2, 4, 8, 16 are accepted.
+ *   Eq. 1  least-squares misfit phi = ||d_mod - d_obs||^2 (summed over shots),
+ *          and its exact gradient with respect to the model velocity
+ *          (Section 1: "misfit evaluation and computation of its gradient").
+ *
+ * Conventions shared by every entry point
+ *   - All array pointers are DEVICE pointers owned by the caller, unless the
+ *     name starts with h_ (host pointer).  float is IEEE fp32, int32_t indices.
+ *   - Arrays are C-contiguous, slowest axis first: a 2-D model is [nz][nx], a
+ *     3-D model [nz][ny][nx] (x fastest).  Positions are integer model-grid
+ *     cells in the same axis order: [D] per source, [D] per receiver.
+ *   - The sponge is OUTSIDE the model grid: the library pads the model by
+ *     nsponge cells on every face, copying edge velocities, and holds the
+ *     wavefield at zero beyond the padded grid.
+ *   - Source: one point source per shot; at step n the library adds
+ *     alpha dt^2 src[s][n] / dx^D at the source cell (a discrete delta).
+ *   - Traces: traces[s][n][r] = P^{n+1} at receiver r of shot s, i.e. the
+ *     field at time (n+1) dt; the initial state is P^0 = P^{-1} = 0.
+ *   - dv is d(phi)/d(v) on the model grid, summed over shots, with the sponge
+ *     damping held fixed.  Outputs are overwritten, never accumulated.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream) and
+ *     runs asynchronously; results are valid once the stream is synchronised.
+ *     A call first copies the (small) position arrays to the host and
+ *     synchronises `stream` once, to validate them.
+ *   - Workspaces: the caller allocates `ws` (>= the size reported by
+ *     fwi_workspace_bytes, 256-byte aligned) and keeps it alive until the
+ *     stream has finished the call's work.  The library allocates no device
+ *     memory and keeps none between calls.  Calls on distinct workspaces are
+ *     independent.
+ *
+ * Errors: every entry point returns an int status (FWI_OK == 0, negative on
+ * error).  All argument checks happen on the host before any kernel is
+ * launched, and on error no output is written.  Asynchronous device faults
+ * surface as FWI_EHIP on a later call.  No C++ exception crosses the ABI.
+ */
+#ifndef FWI_H
+#define FWI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fwi_status {
+    FWI_OK = 0,
+    FWI_EINVAL = -1,      /* malformed problem description or argument */
+    FWI_ECFL = -2,        /* v_max dt / dx above the stability limit of the order */
+    FWI_EBOUNDS = -3,     /* a source or receiver position outside the model grid */
+    FWI_ENOMEM = -4,      /* workspace (or checkpoint buffer) smaller than required */
+    FWI_EHIP = -5,        /* a HIP runtime call failed (message: fwi_last_error) */
+    FWI_ENONFINITE = -6,  /* the wavefield became non-finite */
+    FWI_EUNSUPPORTED = -7 /* valid request this build does not implement */
+};
+
+enum fwi_mode {
+    FWI_MODE_FORWARD = 0,      /* fwi_forward */
+    FWI_MODE_GRADIENT = 1,     /* fwi_gradient */
+    FWI_MODE_FORWARD_CKPT = 2, /* workspace of fwi_forward_ckpt (excluding ckpt_buf) */
+    FWI_MODE_BACKWARD = 3,     /* workspace of fwi_backward (excluding ckpt_buf) */
+    FWI_MODE_CKPT_BUF = 4      /* the checkpoint buffer of forward_ckpt / backward */
+};
+
+enum fwi_ckpt_kind {
+    FWI_CKPT_ALL = 0,     /* keep every time level (small problems, tests) */
+    FWI_CKPT_EVERY = 1,   /* snapshot every `every` steps, recompute segments */
+    FWI_CKPT_REVOLVE = 2  /* binomial (revolve) schedule over `slots` snapshots */
+};
+
+/* One propagation problem: model grid, discretisation and acquisition size. */
+typedef struct fwi_problem {
+    int32_t ndim;       /* 2 or 3 */
+    int32_t shape[3];   /* model grid, slowest axis first ({nz, nx} or {nz, ny, nx}) */
+    float dx;           /* grid spacing (m), the same on every axis, > 0 */
+    float dt;           /* time step (s), > 0 */
+    int32_t nt;         /* number of time steps, >= 1 */
+    int32_t order;      /* spatial order 2M: 2, 4, 8 or 16 */
+    int32_t nsponge;    /* sponge width nb in cells (>= 0), added on every face */
+    float eta_max;      /* peak sponge damping rate (1/s), >= 0 */
+    int32_t nshots;     /* shots, >= 1 */
+    int32_t nrec;       /* receivers per shot, >= 0 */
+} fwi_problem;
+
+/* Checkpointing policy of the gradient. */
+typedef struct fwi_ckpt {
+    int32_t kind;          /* enum fwi_ckpt_kind */
+    int32_t every;         /* FWI_CKPT_EVERY: interval k >= 1 */
+    int32_t slots;         /* FWI_CKPT_REVOLVE: snapshot slots (0: from budget) */
+    int32_t reserved;      /* must be 0 */
+    uint64_t budget_bytes; /* FWI_CKPT_REVOLVE with slots == 0: snapshot budget */
+} fwi_ckpt;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *fwi_strerror(int status);
+
+/* Detail of the last error raised on the calling thread (static per thread). */
+const char *fwi_last_error(void);
+
+/* Largest v_max dt / dx the leapfrog of this order tolerates in ndim
+ * dimensions: sqrt(4 / (ndim * S)), S the largest symbol of one axis of the
+ * central stencil (Section 3 stencils).  Host-only. */
+int fwi_cfl_limit(int32_t ndim, int32_t order, double *h_cfl_max);
+
+/* Workspace bytes needed by an entry point (enum fwi_mode) for `prob`;
+ * `ckpt` is read by the gradient modes and may be NULL otherwise.  Host-only. */
+int fwi_workspace_bytes(const fwi_problem *prob, int32_t mode, const fwi_ckpt *ckpt,
+                        uint64_t *h_bytes);
+
+/*
+ * Forward modelling (Eq. 3 with sponge, Fig. 3 stencil): every shot is
+ * propagated nt steps through the padded model and sampled at its receivers.
+ *   v        [model grid] velocity (m/s), > 0
+ *   src      [nshots][nt] source wavelet samples, src[s][n] = w_s(n dt)
+ *   src_pos  [nshots][ndim]
+ *   rec_pos  [nshots][nrec][ndim]
+ *   traces   [nshots][nt][nrec] output
+ */
+int fwi_forward(const fwi_problem *prob, const float *v, const float *src,
+                const int32_t *src_pos, const int32_t *rec_pos, float *traces,
+                void *ws, uint64_t ws_bytes, void *stream);
+
+/*
+ * Misfit (Eq. 1) and its gradient with respect to v: forward with
+ * checkpoints, residual 2 (d - d_obs), adjoint propagation and the
+ * imaging-condition gradient, recomputing the forward field as `ckpt` says.
+ *   obs            [nshots][nt][nrec] observed traces
+ *   h_misfit       host double: sum over shots, steps, receivers of (d - obs)^2
+ *   dv             [model grid] output, sum over shots
+ *   traces_or_null [nshots][nt][nrec] modelled traces, or NULL
+ */
+int fwi_gradient(const fwi_problem *prob, const float *v, const float *src,
+                 const int32_t *src_pos, const int32_t *rec_pos, const float *obs,
+                 const fwi_ckpt *ckpt, double *h_misfit, float *dv, float *traces_or_null,
+                 void *ws, uint64_t ws_bytes, void *stream);
+
+/*
+ * The forward half of a differentiable forward: as fwi_forward, and also
+ * stores into ckpt_buf (size: FWI_MODE_CKPT_BUF) what fwi_backward needs to
+ * recompute the wavefield under policy `ckpt`.
+ */
+int fwi_forward_ckpt(const fwi_problem *prob, const float *v, const float *src,
+                     const int32_t *src_pos, const int32_t *rec_pos, const fwi_ckpt *ckpt,
+                     float *traces, void *ckpt_buf, uint64_t ckpt_bytes,
+                     void *ws, uint64_t ws_bytes, void *stream);
+
+/*
+ * Vector-Jacobian product of fwi_forward with respect to v: given
+ * grad_traces = d(loss)/d(traces) [nshots][nt][nrec], writes
+ * dv = d(loss)/d(v) [model grid] (sum over shots).  ckpt_buf must hold what
+ * fwi_forward_ckpt stored for the same prob, v, src, positions and ckpt; the
+ * call recomputes wavefields inside it, so it is consumed (its contents are
+ * undefined afterwards and a second backward needs a new forward_ckpt).
+ */
+int fwi_backward(const fwi_problem *prob, const float *v, const float *src,
+                 const int32_t *src_pos, const int32_t *rec_pos, const fwi_ckpt *ckpt,
+                 void *ckpt_buf, uint64_t ckpt_bytes, const float *grad_traces,
+                 float *dv, void *ws, uint64_t ws_bytes, void *stream);
+
+/*
+ * Smallest and largest velocity of a model of n cells (device array v), e.g.
+ * to choose dt and the sponge's eta_max.  ws: device scratch of at least
+ * 4096 bytes.  Synchronises `stream`.  FWI_EINVAL if a value is not finite.
+ */
+int fwi_velocity_range(const float *v, int64_t n, float *h_vmin, float *h_vmax, void *ws,
+                       uint64_t ws_bytes, void *stream);
+
+/*
+ * Binomial checkpointing schedule (revolve, Griewank & Walther) for
+ * reversing `nsteps` forward steps with `slots` snapshot slots, the initial
+ * state being free (it is zero).  Host-only.  Writes up to `cap` actions as
+ * (opcode, argument) pairs into h_actions (may be NULL with cap 0), their
+ * count into h_count, and the number of forward steps the schedule performs
+ * (initial sweep included) into h_forward_steps.
+ *   opcodes: 1 ADVANCE(to time), 2 TAKESHOT(slot), 3 RESTORE(slot, time is the
+ *            slot's), 4 ADJOINT(time k: consume state k), 5 RESTART (state 0).
+ */
+int fwi_revolve_schedule(int32_t nsteps, int32_t slots, int32_t *h_actions, int64_t cap,
+                         int64_t *h_count, int64_t *h_forward_steps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FWI_H */

@@ -1,0 +1,165 @@
+"""torch-level entry points: forward() and gradient() on device tensors.
+
+torch supplies device memory (tensors, workspaces from its caching allocator)
+and the stream; every step of the computation runs in libfwi.so's kernels.
+Shapes follow include/fwi.h: v [nz][nx] or [nz][ny][nx] float32, src
+[S][nt] float32, src_pos [S][D] int32, rec_pos [S][R][D] (or [R][D], shared
+by every shot) int32, traces [S][nt][R] float32.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _require(t: torch.Tensor, name: str, dtype: torch.dtype):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch.Tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a device (cuda) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    return t.contiguous()
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    """Discretisation shared by forward/gradient calls."""
+    dt: float
+    dx: float
+    order: int = 8
+    nsponge: int = 20
+    eta_max: Optional[float] = None   # None: 3 vmax ln(1000) / (2 nsponge dx)
+    ckpt: str = "every:50"            # "all", "every:K", "revolve:SLOTS", "revolve:BUDGETe9B"
+
+
+def parse_ckpt(spec: str) -> _lib.FwiCkpt:
+    c = _lib.FwiCkpt()
+    if spec == "all":
+        c.kind = _lib.CKPT_ALL
+    elif spec.startswith("every:"):
+        c.kind = _lib.CKPT_EVERY
+        c.every = int(spec.split(":")[1])
+    elif spec.startswith("revolve:"):
+        c.kind = _lib.CKPT_REVOLVE
+        arg = spec.split(":")[1]
+        if "e" in arg or "." in arg:   # a byte budget such as 40e9
+            c.budget_bytes = int(float(arg))
+        else:
+            c.slots = int(arg)
+    else:
+        raise ValueError("checkpoint spec must be all, every:K or revolve:SLOTS|BUDGET")
+    return c
+
+
+def _shots(v, src, src_pos, rec_pos):
+    D = v.dim()
+    if D not in (2, 3):
+        raise ValueError("v must be 2-D or 3-D")
+    src = src.reshape(-1, src.shape[-1]) if src.dim() == 1 else src
+    src_pos = src_pos.reshape(-1, D)
+    S = src_pos.shape[0]
+    if src.shape[0] == 1 and S > 1:
+        src = src.expand(S, src.shape[1])
+    if rec_pos.dim() == 2:
+        rec_pos = rec_pos.unsqueeze(0).expand(S, rec_pos.shape[0], D)
+    return src.contiguous(), src_pos.contiguous(), rec_pos.contiguous()
+
+
+def default_eta_max(vmax: float, nsponge: int, dx: float) -> float:
+    if nsponge <= 0:
+        return 0.0
+    return 3.0 * vmax * math.log(1000.0) / (2.0 * nsponge * dx)
+
+
+def velocity_range(v: torch.Tensor):
+    v = _require(v, "v", torch.float32)
+    ws = torch.empty(4096, dtype=torch.uint8, device=v.device)
+    return _lib.fwi_velocity_range(v.data_ptr(), v.numel(), ws.data_ptr(), ws.numel(),
+                                   torch.cuda.current_stream(v.device).cuda_stream)
+
+
+def make_problem(v, nt, cfg: Config, nshots, nrec) -> _lib.FwiProblem:
+    p = _lib.FwiProblem()
+    p.ndim = v.dim()
+    for i, n in enumerate(v.shape):
+        p.shape[i] = int(n)
+    p.dx, p.dt, p.nt = float(cfg.dx), float(cfg.dt), int(nt)
+    p.order, p.nsponge = int(cfg.order), int(cfg.nsponge)
+    eta = cfg.eta_max
+    if eta is None:
+        eta = default_eta_max(velocity_range(v)[1], cfg.nsponge, cfg.dx)
+    p.eta_max = float(eta)
+    p.nshots, p.nrec = int(nshots), int(nrec)
+    return p
+
+
+class Workspace:
+    """A reusable device workspace (grows on demand, 256-byte aligned via torch)."""
+
+    def __init__(self, device=None):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes, device):
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = None
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        return self.buf
+
+
+def forward(v, src, src_pos, rec_pos, cfg: Config, nt: Optional[int] = None,
+            workspace: Optional[Workspace] = None, out: Optional[torch.Tensor] = None):
+    """Forward modelling through fwi_forward; returns traces [S][nt][R]."""
+    v = _require(v, "v", torch.float32)
+    src = _require(src, "src", torch.float32)
+    src_pos = _require(src_pos, "src_pos", torch.int32)
+    rec_pos = _require(rec_pos, "rec_pos", torch.int32)
+    src, src_pos, rec_pos = _shots(v, src, src_pos, rec_pos)
+    S, R = src_pos.shape[0], rec_pos.shape[1]
+    nt = src.shape[1] if nt is None else int(nt)
+    prob = make_problem(v, nt, cfg, S, R)
+    nbytes = _lib.fwi_workspace_bytes(prob, _lib.MODE_FORWARD)
+    ws = (workspace or Workspace()).get(nbytes, v.device)
+    traces = out if out is not None else torch.empty((S, nt, R), dtype=torch.float32,
+                                                     device=v.device)
+    _lib.fwi_forward(prob, v.data_ptr(), src.data_ptr(), src_pos.data_ptr(),
+                     _ptr(rec_pos) if R else None, _ptr(traces) if R else None,
+                     ws.data_ptr(), ws.numel(), torch.cuda.current_stream(v.device).cuda_stream)
+    return traces
+
+
+def gradient(v, obs, src, src_pos, rec_pos, cfg: Config, return_traces=False,
+             workspace: Optional[Workspace] = None):
+    """Misfit (Eq. 1) and d(misfit)/d(v) through fwi_gradient."""
+    v = _require(v, "v", torch.float32)
+    obs = _require(obs, "obs", torch.float32)
+    src = _require(src, "src", torch.float32)
+    src_pos = _require(src_pos, "src_pos", torch.int32)
+    rec_pos = _require(rec_pos, "rec_pos", torch.int32)
+    src, src_pos, rec_pos = _shots(v, src, src_pos, rec_pos)
+    S, R = src_pos.shape[0], rec_pos.shape[1]
+    nt = src.shape[1]
+    prob = make_problem(v, nt, cfg, S, R)
+    ck = parse_ckpt(cfg.ckpt)
+    nbytes = _lib.fwi_workspace_bytes(prob, _lib.MODE_GRADIENT, ck)
+    ws = (workspace or Workspace()).get(nbytes, v.device)
+    dv = torch.empty_like(v)
+    traces = torch.empty((S, nt, R), dtype=torch.float32, device=v.device) if return_traces else None
+    mis = _lib.fwi_gradient(prob, v.data_ptr(), src.data_ptr(), src_pos.data_ptr(),
+                            _ptr(rec_pos) if R else None, _ptr(obs) if R else None, ck,
+                            dv.data_ptr(), _ptr(traces), ws.data_ptr(), ws.numel(),
+                            torch.cuda.current_stream(v.device).cuda_stream)
+    if return_traces:
+        return mis, dv, traces
+    return mis, dv

@@ -1,0 +1,63 @@
+// fwi_internal.h -- device-side job table shared by the HIP kernels and the
+// host runtime of libfwi.so (not part of the public C ABI).
+//
+// Field layout in HBM (one fp32 "field" = one padded grid plus a zero frame):
+//   padded grid = model grid + nb sponge cells on every face (nz, ny, nx;
+//   ny == 1 in 2-D), surrounded by M = order/2 ghost cells that stay zero
+//   (the Dirichlet frame the star stencil reads past the sponge).
+//   element (z, y, x) of the padded grid lives at
+//       ((z + M) * nya + (y + gy)) * pitch + (x + M)
+//   with gy = M in 3-D (0 in 2-D), nya = ny + 2 gy rows per plane and pitch a
+//   multiple of 64 floats (256 B), so every row starts on a 256-byte line.
+//   Tiles are aligned to memory columns [64 t, 64 t + 64), not to the grid:
+//   each wavefront then loads and stores whole aligned 256-byte segments.
+#pragma once
+#include <stdint.h>
+
+namespace fwi {
+
+constexpr int kTileX = 64;   // memory columns per tile (one wavefront)
+constexpr int kRowsPerWave = 4;   // 3-D: y rows per thread (register blocking)
+constexpr int kWaves3d = 4;  // 3-D: wavefronts per block
+constexpr int kTileY = kRowsPerWave * kWaves3d;   // 3-D tile height in y
+constexpr int kGatherThreads = 256;
+
+struct Job {
+    // geometry of the padded grid and its field layout
+    int32_t nz, ny, nx;    // padded grid (ny == 1 in 2-D)
+    int32_t pitch;         // floats per row
+    int32_t nya;           // rows per plane, ghost rows included
+    int32_t nb;            // sponge width
+    int64_t plane;         // floats per plane (nya * pitch)
+    int64_t fstride;       // floats per field allocation
+    float eta_dt;          // eta_max * dt / nb^2: eta*dt = eta_dt * sum_a d_a^2
+    float src_scale;       // dt^2 / dx^D
+    // tiling of the step kernels
+    int32_t ntx, nty, nzc, zc;   // tiles in x and y, z chunks and chunk length
+    int32_t ntiles;              // ntx * nty * nzc
+    int32_t ngather;             // gather blocks (forward record)
+    // time: forward n = n0 + step, adjoint k = k0 - step
+    int32_t n0;
+    int32_t k0;
+    int32_t nt;
+    int32_t record;        // forward: write traces
+    int32_t accumulate;    // adjoint: accumulate the gradient
+    // fields
+    const float *kappa;    // (v dt / dx)^2 on the padded grid (frame = 0)
+    float *ring;           // forward wavefield ring, level n in slot n mod R
+    int32_t R;
+    float *adj;            // adjoint ring, level k in slot k mod 2
+    float *grad;           // sum_n psi^{n+1} * lap'(p^n)
+    float *snap;           // snapshot store, slot s holds 2 fields
+    // point source (padded coordinates, -1: none)
+    int32_t src_z, src_y, src_x;
+    int32_t nrec;
+    const float *wavelet;  // [nt]
+    const int64_t *rec_off;    // [nrec] field offsets of the receiver cells
+    const int32_t *rec_next;   // [nrec] next receiver on the same cell, -1 at the end
+    const int32_t *rec_head;   // [nrec] 1 for the first receiver of its cell
+    float *traces;         // [nt][nrec]
+    const float *res;      // [nt][nrec] adjoint source
+};
+
+}  // namespace fwi

@@ -1,0 +1,809 @@
+// fwi_runtime.cpp -- host runtime and C ABI of libfwi.so.
+//
+// Validates arguments on the host, lays the caller's workspace out into
+// fields and tables, and drives the time loops: the forward sweep (Eq. 3 with
+// sponge), the misfit (Eq. 1), and the adjoint sweep with the imaging
+// condition, recomputing forward levels from checkpoints (every-k segments or
+// a binomial revolve schedule).  Every shot of a call is one job of a job
+// table, so each launch advances all shots at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fwi.h"
+#include "fwi_internal.h"
+#include "revolve.h"
+
+namespace fwi {
+void launch_step(int ndim, int M, bool adj, const Job *jobs, const int *prefix, int njobs,
+                 int step, int ttiles, int gblocks, int remap, hipStream_t st);
+void launch_prep_kappa(const float *v, float *kappa, int M, int gy, int nz, int ny, int nx,
+                       int pitch, int nya, int nb, int nzm, int nym, int nxm, int64_t total,
+                       float dt_dx, hipStream_t st);
+void launch_fill(float *p, int64_t n, float val, hipStream_t st);
+void launch_snapshot(const Job *jobs, int njobs, int64_t fstride, int slot, int time, int dir,
+                     hipStream_t st);
+void launch_gather(const Job *jobs, const int *gprefix, int njobs, int gblocks, int threads,
+                   int step, hipStream_t st);
+void launch_adj_inject(const Job *jobs, const int *gprefix, int njobs, int gblocks, int threads,
+                       int step, hipStream_t st);
+int misfit_partials();
+void launch_misfit(const float *d, const float *obs, float *res, int64_t n, double *partial,
+                   double *out, hipStream_t st);
+void launch_fold(int ndim, const Job *jobs, int njobs, int M, int gy, int nz, int ny, int nx,
+                 int nb, int nzm, int nym, int nxm, float *tmp1, float *tmp2, const float *v,
+                 float *dv, hipStream_t st);
+int vstats_blocks();
+void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st);
+}  // namespace fwi
+
+using namespace fwi;
+
+// ------------------------------------------------------------------ errors
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(FWI_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));       \
+    } while (0)
+
+// ---------------------------------------------------------------- geometry
+namespace {
+
+constexpr uint64_t kAlign = 256;
+
+uint64_t align_up(uint64_t a, uint64_t b) { return (a + b - 1) / b * b; }
+
+struct Geometry {
+    int ndim = 0, M = 0, gy = 0;
+    int nzm = 1, nym = 1, nxm = 1;   // model grid
+    int nb = 0;
+    int nz = 1, ny = 1, nx = 1;      // padded grid
+    int pitch = 0, nya = 0;
+    int64_t plane = 0, fstride = 0;
+    int64_t model_cells = 0;
+};
+
+int check_problem(const fwi_problem *p)
+{
+    if (!p) return fail(FWI_EINVAL, "problem is NULL");
+    if (p->ndim != 2 && p->ndim != 3) return fail(FWI_EINVAL, "ndim must be 2 or 3");
+    for (int a = 0; a < p->ndim; ++a)
+        if (p->shape[a] < 1 || p->shape[a] > (1 << 20))
+            return fail(FWI_EINVAL, "shape[%d] = %d out of range", a, p->shape[a]);
+    if (!(p->dx > 0.f) || !std::isfinite(p->dx)) return fail(FWI_EINVAL, "dx must be > 0");
+    if (!(p->dt > 0.f) || !std::isfinite(p->dt)) return fail(FWI_EINVAL, "dt must be > 0");
+    if (p->nt < 1) return fail(FWI_EINVAL, "nt must be >= 1");
+    if (p->order != 2 && p->order != 4 && p->order != 8 && p->order != 16)
+        return fail(FWI_EINVAL, "order must be 2, 4, 8 or 16");
+    if (p->nsponge < 0 || p->nsponge > 4096) return fail(FWI_EINVAL, "nsponge out of range");
+    if (!(p->eta_max >= 0.f) || !std::isfinite(p->eta_max))
+        return fail(FWI_EINVAL, "eta_max must be finite and >= 0");
+    if (p->nshots < 1) return fail(FWI_EINVAL, "nshots must be >= 1");
+    if (p->nrec < 0) return fail(FWI_EINVAL, "nrec must be >= 0");
+    return FWI_OK;
+}
+
+int make_geometry(const fwi_problem *p, Geometry *g)
+{
+    int st = check_problem(p);
+    if (st) return st;
+    g->ndim = p->ndim;
+    g->M = p->order / 2;
+    g->gy = p->ndim == 3 ? g->M : 0;
+    g->nb = p->nsponge;
+    g->nzm = p->shape[0];
+    g->nym = p->ndim == 3 ? p->shape[1] : 1;
+    g->nxm = p->ndim == 3 ? p->shape[2] : p->shape[1];
+    g->nz = g->nzm + 2 * g->nb;
+    g->ny = p->ndim == 3 ? g->nym + 2 * g->nb : 1;
+    g->nx = g->nxm + 2 * g->nb;
+    g->pitch = (int)align_up((uint64_t)g->nx + 2 * g->M, 64);
+    g->nya = g->ny + 2 * g->gy;
+    g->plane = (int64_t)g->nya * g->pitch;
+    g->fstride = (int64_t)(g->nz + 2 * g->M) * g->plane;
+    g->model_cells = (int64_t)g->nzm * g->nym * g->nxm;
+    if (g->fstride > (int64_t(1) << 40)) return fail(FWI_EINVAL, "grid too large");
+    return FWI_OK;
+}
+
+// largest symbol of one axis of the central stencil, S = max_k -(c0 + 2 sum c_m cos(mk))
+double max_symbol(int order)
+{
+    const int M = order / 2;
+    double fM = 1;
+    for (int i = 2; i <= M; ++i) fM *= i;
+    std::vector<double> c(M + 1, 0.0);
+    for (int m = 1; m <= M; ++m) {
+        double a = 1, b = 1;
+        for (int i = 2; i <= M - m; ++i) a *= i;
+        for (int i = 2; i <= M + m; ++i) b *= i;
+        c[m] = 2.0 * ((m & 1) ? 1.0 : -1.0) * fM * fM / (double(m) * m * a * b);
+        c[0] -= 2.0 * c[m];
+    }
+    double best = 0;
+    const int K = 20000;
+    for (int i = 0; i <= K; ++i) {
+        const double k = M_PI * i / K;
+        double s = c[0];
+        for (int m = 1; m <= M; ++m) s += 2.0 * c[m] * std::cos(m * k);
+        best = std::max(best, -s);
+    }
+    return best;
+}
+
+struct Policy {
+    int kind = FWI_CKPT_ALL;
+    int every = 0;   // EVERY / ALL: segment length K
+    int R = 2;       // forward ring length
+    int nsnap = 0;   // snapshot slots per shot
+    int ctop = 0;    // EVERY / ALL: base of the segment kept in the ring
+};
+
+int make_policy(const fwi_problem *p, const Geometry &g, int mode, const fwi_ckpt *ck, Policy *po)
+{
+    *po = Policy{};
+    if (mode == FWI_MODE_FORWARD) { po->R = 2; return FWI_OK; }
+    if (!ck) return fail(FWI_EINVAL, "checkpoint policy is NULL");
+    if (ck->reserved != 0) return fail(FWI_EINVAL, "fwi_ckpt.reserved must be 0");
+    const int nt = p->nt;
+    po->kind = ck->kind;
+    switch (ck->kind) {
+    case FWI_CKPT_ALL:
+    case FWI_CKPT_EVERY: {
+        int K = ck->kind == FWI_CKPT_ALL ? nt : ck->every;
+        if (K < 1) return fail(FWI_EINVAL, "every must be >= 1");
+        K = std::min(K, nt);
+        po->every = K;
+        po->R = K + 1;
+        po->ctop = K * ((nt - 1) / K);
+        po->nsnap = std::max(0, po->ctop / K - 1);
+        return FWI_OK;
+    }
+    case FWI_CKPT_REVOLVE: {
+        po->R = 2;
+        if (ck->slots < 0) return fail(FWI_EINVAL, "slots must be >= 0");
+        if (ck->slots > 0) {
+            po->nsnap = ck->slots;
+        } else {
+            const uint64_t per = 2ull * (uint64_t)g.fstride * sizeof(float) * (uint64_t)p->nshots;
+            po->nsnap = (int)std::min<uint64_t>(ck->budget_bytes / per, (uint64_t)nt);
+        }
+        po->nsnap = std::min(po->nsnap, nt);
+        return FWI_OK;
+    }
+    default:
+        return fail(FWI_EINVAL, "unknown checkpoint kind %d", ck->kind);
+    }
+}
+
+// Byte layout of the workspace (ws) and of the checkpoint buffer (ck).
+struct Layout {
+    uint64_t kappa = 0, ring = 0, adj = 0, grad = 0, snap = 0;
+    uint64_t jobs = 0, prefix = 0, rec_off = 0, rec_next = 0, rec_head = 0;
+    uint64_t res = 0, partial = 0, misfit = 0, fold1 = 0, fold2 = 0, vstats = 0;
+    bool ring_in_ws = false, has_adj = false, has_res = false, has_fold = false;
+    uint64_t ws_total = 0, ck_total = 0;
+};
+
+struct Carver {
+    uint64_t off = 0;
+    uint64_t take(uint64_t bytes)
+    {
+        const uint64_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    }
+};
+
+void make_layout(const fwi_problem *p, const Geometry &g, const Policy &po, int mode, Layout *L)
+{
+    *L = Layout{};
+    const uint64_t S = (uint64_t)p->nshots, R = (uint64_t)p->nrec;
+    const uint64_t fb = (uint64_t)g.fstride * sizeof(float);
+    const int njobs = p->nshots;
+    Carver w;
+    L->kappa = w.take(fb);
+    L->jobs = w.take(sizeof(Job) * (uint64_t)njobs);
+    L->prefix = w.take(sizeof(int) * 2ull * (njobs + 1));
+    L->rec_off = w.take(sizeof(int64_t) * S * R + 8);
+    L->rec_next = w.take(sizeof(int32_t) * S * R + 4);
+    L->rec_head = w.take(sizeof(int32_t) * S * R + 4);
+    L->vstats = w.take(sizeof(float) * 3ull * vstats_blocks());
+    if (mode == FWI_MODE_BACKWARD || mode == FWI_MODE_GRADIENT) {
+        L->has_adj = true;
+        L->adj = w.take(2 * fb * S);
+        L->grad = w.take(fb * S);
+        L->has_fold = true;
+        L->fold1 = w.take(sizeof(float) * (uint64_t)g.nz * g.ny * g.nxm);
+        L->fold2 = w.take(sizeof(float) * (uint64_t)g.nz * g.nym * g.nxm);
+    }
+    if (mode == FWI_MODE_GRADIENT) {
+        L->has_res = true;
+        L->res = w.take(sizeof(float) * S * (uint64_t)p->nt * R + 4);
+        L->partial = w.take(sizeof(double) * (uint64_t)misfit_partials());
+        L->misfit = w.take(sizeof(double));
+    }
+    // wavefield ring and snapshots
+    Carver c;
+    const uint64_t ring = c.take(fb * S * (uint64_t)po.R);
+    const uint64_t snap = c.take(2 * fb * S * (uint64_t)po.nsnap);
+    if (mode == FWI_MODE_FORWARD || mode == FWI_MODE_GRADIENT) {
+        L->ring_in_ws = true;
+        const uint64_t base = w.take(c.off);
+        L->ring = base + ring;
+        L->snap = base + snap;
+    } else {
+        L->ring = ring;
+        L->snap = snap;
+    }
+    L->ws_total = w.off;
+    L->ck_total = c.off;
+}
+
+void tiles_for(const Geometry &g, int njobs, int *ntx, int *nty, int *nzc, int *zc)
+{
+    const int M = g.M;
+    *ntx = (g.nx + M + kTileX - 1) / kTileX;
+    *nty = g.ndim == 3 ? (g.ny + kTileY - 1) / kTileY : 1;
+    const int64_t per = (int64_t)(*ntx) * (*nty) * njobs;
+    // enough blocks to fill 256 CUs several times over
+    int64_t target = g.ndim == 3 ? 2048 : 8192;
+    if (const char *e = getenv("FWI_TARGET_BLOCKS")) target = std::max(1, atoi(e));
+    int want = (int)std::max<int64_t>(1, (target + per - 1) / per);
+    int z = (g.nz + want - 1) / want;
+    z = std::max(z, std::min(g.nz, std::max(2 * M, 8)));
+    if (const char *e = getenv("FWI_ZCHUNK")) z = std::max(1, atoi(e));
+    z = std::min(z, g.nz);
+    *zc = z;
+    *nzc = (g.nz + z - 1) / z;
+}
+
+int gather_threads(const Geometry &g) { return g.ndim == 3 ? 256 : 64; }
+
+// ------------------------------------------------------------ call context
+struct Ctx {
+    const fwi_problem *p = nullptr;
+    Geometry g;
+    Policy po;
+    Layout L;
+    hipStream_t st = nullptr;
+    char *ws = nullptr;
+    char *ck = nullptr;
+    std::vector<Job> jobs;
+    Job *d_jobs = nullptr;
+    int *d_prefix = nullptr;
+    int ttiles = 0, gblocks = 0, gthreads = 64;
+    int remap = 1;
+    std::vector<int> slot_time;
+
+    float *f_at(uint64_t off, bool in_ws) const
+    {
+        return reinterpret_cast<float *>((in_ws ? ws : ck) + off);
+    }
+};
+
+int prepare(Ctx &c, const fwi_problem *p, int mode, const fwi_ckpt *ck, void *ws,
+            uint64_t ws_bytes, void *ckbuf, uint64_t ck_bytes, void *stream)
+{
+    int st = make_geometry(p, &c.g);
+    if (st) return st;
+    c.p = p;
+    st = make_policy(p, c.g, mode, ck, &c.po);
+    if (st) return st;
+    make_layout(p, c.g, c.po, mode, &c.L);
+    if (!ws) return fail(FWI_EINVAL, "workspace is NULL");
+    if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0)
+        return fail(FWI_EINVAL, "workspace must be 256-byte aligned");
+    if (ws_bytes < c.L.ws_total)
+        return fail(FWI_ENOMEM, "workspace too small: %llu < %llu bytes",
+                    (unsigned long long)ws_bytes, (unsigned long long)c.L.ws_total);
+    if (!c.L.ring_in_ws) {
+        if (!ckbuf) return fail(FWI_EINVAL, "checkpoint buffer is NULL");
+        if ((reinterpret_cast<uintptr_t>(ckbuf) & (kAlign - 1)) != 0)
+            return fail(FWI_EINVAL, "checkpoint buffer must be 256-byte aligned");
+        if (ck_bytes < c.L.ck_total)
+            return fail(FWI_ENOMEM, "checkpoint buffer too small: %llu < %llu bytes",
+                        (unsigned long long)ck_bytes, (unsigned long long)c.L.ck_total);
+    }
+    c.ws = static_cast<char *>(ws);
+    c.ck = static_cast<char *>(ckbuf);
+    c.st = static_cast<hipStream_t>(stream);
+    if (const char *e = getenv("FWI_XCD_REMAP")) c.remap = atoi(e) != 0;
+    return FWI_OK;
+}
+
+// Reads positions and model statistics back, checks them, and uploads the
+// job table.  res: adjoint source (or NULL); traces: recording target (or NULL).
+int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
+          const int32_t *rec_pos, float *traces, const float *res, int accumulate)
+{
+    const fwi_problem *p = c.p;
+    const Geometry &g = c.g;
+    const int S = p->nshots, R = p->nrec, D = p->ndim;
+    if (!v || !src_pos || (R > 0 && !rec_pos)) return fail(FWI_EINVAL, "NULL input array");
+    std::vector<int32_t> hs((size_t)S * D), hr((size_t)S * R * D);
+    HIP_TRY(hipMemcpyAsync(hs.data(), src_pos, hs.size() * 4, hipMemcpyDeviceToHost, c.st));
+    if (!hr.empty())
+        HIP_TRY(hipMemcpyAsync(hr.data(), rec_pos, hr.size() * 4, hipMemcpyDeviceToHost, c.st));
+    float *d_vs = c.f_at(c.L.vstats, true);
+    launch_vstats(v, g.model_cells, d_vs, c.st);
+    HIP_TRY(hipGetLastError());
+    std::vector<float> hv(3 * (size_t)vstats_blocks());
+    HIP_TRY(hipMemcpyAsync(hv.data(), d_vs, hv.size() * 4, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+
+    const int dims[3] = {g.nzm, g.nym, g.nxm};
+    auto in_model = [&](const int32_t *q) {
+        if (D == 2) return q[0] >= 0 && q[0] < dims[0] && q[1] >= 0 && q[1] < dims[2];
+        return q[0] >= 0 && q[0] < dims[0] && q[1] >= 0 && q[1] < dims[1] && q[2] >= 0 &&
+               q[2] < dims[2];
+    };
+    for (int s = 0; s < S; ++s)
+        if (!in_model(&hs[(size_t)s * D])) return fail(FWI_EBOUNDS, "source %d outside the model", s);
+    for (size_t r = 0; r < (size_t)S * R; ++r)
+        if (!in_model(&hr[r * D])) return fail(FWI_EBOUNDS, "receiver %zu outside the model", r);
+
+    const int B = vstats_blocks();
+    float vmin = INFINITY, vmax = -INFINITY, bad = 0.f;
+    for (int i = 0; i < B; ++i) {
+        vmin = std::min(vmin, hv[i]);
+        vmax = std::max(vmax, hv[B + i]);
+        bad += hv[2 * B + i];
+    }
+    if (bad > 0.f) return fail(FWI_EINVAL, "velocity has non-finite values");
+    if (!(vmin > 0.f)) return fail(FWI_EINVAL, "velocity must be > 0 (min %g)", (double)vmin);
+    const double cfl = (double)vmax * p->dt / p->dx;
+    const double lim = std::sqrt(4.0 / (p->ndim * max_symbol(p->order)));
+    if (cfl > lim) return fail(FWI_ECFL, "v_max dt / dx = %.4f exceeds %.4f", cfl, lim);
+
+    // receiver offsets and duplicate chains (receivers sharing a cell)
+    auto offset = [&](const int32_t *q) -> int64_t {
+        const int z = q[0] + g.nb;
+        const int y = D == 3 ? q[1] + g.nb : 0;
+        const int x = (D == 3 ? q[2] : q[1]) + g.nb;
+        return ((int64_t)(z + g.M) * g.nya + (y + g.gy)) * g.pitch + (x + g.M);
+    };
+    std::vector<int64_t> roff((size_t)S * R);
+    std::vector<int32_t> rnext((size_t)S * R, -1), rhead((size_t)S * R, 0);
+    std::vector<int32_t> order(R);
+    for (int s = 0; s < S; ++s) {
+        int64_t *o = roff.data() + (size_t)s * R;
+        for (int r = 0; r < R; ++r) o[r] = offset(&hr[((size_t)s * R + r) * D]);
+        for (int r = 0; r < R; ++r) order[r] = r;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return o[a] < o[b]; });
+        for (int i = 0; i < R; ++i) {
+            const int r = order[i];
+            const bool first = i == 0 || o[order[i - 1]] != o[r];
+            rhead[(size_t)s * R + r] = first ? 1 : 0;
+            if (i + 1 < R && o[order[i + 1]] == o[r]) rnext[(size_t)s * R + r] = order[i + 1];
+        }
+    }
+
+    // job table: one job per shot
+    int ntx, nty, nzc, zc;
+    tiles_for(g, S, &ntx, &nty, &nzc, &zc);
+    c.gthreads = gather_threads(g);
+    const int ng = (R + c.gthreads - 1) / c.gthreads;
+    const uint64_t fs = (uint64_t)g.fstride;
+    float *kappa = c.f_at(c.L.kappa, true);
+    float *ring = c.f_at(c.L.ring, c.L.ring_in_ws);
+    float *snap = c.f_at(c.L.snap, c.L.ring_in_ws);
+    float *adj = c.L.has_adj ? c.f_at(c.L.adj, true) : nullptr;
+    float *grad = c.L.has_adj ? c.f_at(c.L.grad, true) : nullptr;
+    int64_t *d_roff = reinterpret_cast<int64_t *>(c.ws + c.L.rec_off);
+    int32_t *d_rnext = reinterpret_cast<int32_t *>(c.ws + c.L.rec_next);
+    int32_t *d_rhead = reinterpret_cast<int32_t *>(c.ws + c.L.rec_head);
+    double cell = 1.0;
+    for (int a = 0; a < D; ++a) cell *= p->dx;
+    c.jobs.assign(S, Job{});
+    std::vector<int> prefix(2 * (S + 1), 0);
+    for (int s = 0; s < S; ++s) {
+        Job &J = c.jobs[s];
+        J.nz = g.nz; J.ny = g.ny; J.nx = g.nx;
+        J.pitch = g.pitch; J.nya = g.nya; J.nb = g.nb;
+        J.plane = g.plane; J.fstride = g.fstride;
+        J.eta_dt = g.nb > 0 ? (float)((double)p->eta_max * p->dt / ((double)g.nb * g.nb)) : 0.f;
+        J.src_scale = (float)((double)p->dt * p->dt / cell);
+        J.ntx = ntx; J.nty = nty; J.nzc = nzc; J.zc = zc;
+        J.ntiles = ntx * nty * nzc;
+        J.ngather = ng;
+        J.n0 = 0; J.k0 = 0; J.nt = p->nt;
+        J.record = traces != nullptr;
+        J.accumulate = accumulate;
+        J.kappa = kappa;
+        J.ring = ring + (uint64_t)s * c.po.R * fs;
+        J.R = c.po.R;
+        J.adj = adj ? adj + (uint64_t)s * 2 * fs : nullptr;
+        J.grad = grad ? grad + (uint64_t)s * fs : nullptr;
+        J.snap = c.po.nsnap > 0 ? snap + (uint64_t)s * 2 * c.po.nsnap * fs : nullptr;
+        const int32_t *q = &hs[(size_t)s * D];
+        J.src_z = q[0] + g.nb;
+        J.src_y = D == 3 ? q[1] + g.nb : 0;
+        J.src_x = (D == 3 ? q[2] : q[1]) + g.nb;
+        J.nrec = R;
+        J.wavelet = src ? src + (size_t)s * p->nt : nullptr;
+        J.rec_off = d_roff + (size_t)s * R;
+        J.rec_next = d_rnext + (size_t)s * R;
+        J.rec_head = d_rhead + (size_t)s * R;
+        J.traces = traces ? traces + (size_t)s * p->nt * R : nullptr;
+        J.res = res ? res + (size_t)s * p->nt * R : nullptr;
+        prefix[s + 1] = prefix[s] + J.ntiles;
+        prefix[S + 1 + s + 1] = prefix[S + 1 + s] + ng;
+    }
+    c.ttiles = prefix[S];
+    c.gblocks = prefix[2 * S + 1];
+    c.d_jobs = reinterpret_cast<Job *>(c.ws + c.L.jobs);
+    c.d_prefix = reinterpret_cast<int *>(c.ws + c.L.prefix);
+    HIP_TRY(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(Job) * S, hipMemcpyHostToDevice, c.st));
+    HIP_TRY(hipMemcpyAsync(c.d_prefix, prefix.data(), sizeof(int) * prefix.size(),
+                           hipMemcpyHostToDevice, c.st));
+    if (R > 0) {
+        HIP_TRY(hipMemcpyAsync(d_roff, roff.data(), roff.size() * 8, hipMemcpyHostToDevice, c.st));
+        HIP_TRY(hipMemcpyAsync(d_rnext, rnext.data(), rnext.size() * 4, hipMemcpyHostToDevice, c.st));
+        HIP_TRY(hipMemcpyAsync(d_rhead, rhead.data(), rhead.size() * 4, hipMemcpyHostToDevice, c.st));
+    }
+    // model -> kappa' = (v dt/dx)^2 on the padded grid
+    launch_prep_kappa(v, kappa, g.M, g.gy, g.nz, g.ny, g.nx, g.pitch, g.nya, g.nb, g.nzm, g.nym,
+                      g.nxm, g.fstride, (float)((double)p->dt / p->dx), c.st);
+    HIP_TRY(hipGetLastError());
+    // host staging vectors die with this frame: finish the uploads now
+    HIP_TRY(hipStreamSynchronize(c.st));
+    return FWI_OK;
+}
+
+// ------------------------------------------------------------ time loops
+int fwd_step(Ctx &c, int n, bool record)
+{
+    launch_step(c.g.ndim, c.g.M, false, c.d_jobs, c.d_prefix, c.p->nshots, n, c.ttiles,
+                record ? c.gblocks : 0, c.remap, c.st);
+    return FWI_OK;
+}
+
+int adj_step(Ctx &c, int k)
+{
+    launch_step(c.g.ndim, c.g.M, true, c.d_jobs, c.d_prefix, c.p->nshots, -k, c.ttiles, 0,
+                c.remap, c.st);
+    launch_adj_inject(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
+                      c.gthreads, -k, c.st);
+    return FWI_OK;
+}
+
+int snapshot(Ctx &c, int slot, int time, int dir)
+{
+    if (dir != 2 && (slot < 0 || slot >= c.po.nsnap))
+        return fail(FWI_EINVAL, "internal: snapshot slot %d of %d", slot, c.po.nsnap);
+    launch_snapshot(c.d_jobs, c.p->nshots, c.g.fstride, slot, time, dir, c.st);
+    return FWI_OK;
+}
+
+#define TRY(x)                   \
+    do {                         \
+        const int s_ = (x);      \
+        if (s_) return s_;       \
+    } while (0)
+
+void zero(float *p, uint64_t floats, hipStream_t st) { launch_fill(p, (int64_t)floats, 0.f, st); }
+
+// Forward sweep 0 -> nt recording traces and taking the policy's snapshots.
+int forward_phase(Ctx &c, bool record)
+{
+    const int nt = c.p->nt;
+    const uint64_t fs = (uint64_t)c.g.fstride;
+    zero(c.jobs[0].ring, fs * c.po.R * c.p->nshots, c.st);
+    if (c.po.kind == FWI_CKPT_REVOLVE) {
+        int64_t steps = 0;
+        std::vector<Action> acts = revolve_schedule(nt, c.po.nsnap, &steps);
+        c.slot_time.assign(std::max(c.po.nsnap, 1), -1);
+        int cur = 0;
+        for (const Action &a : acts) {
+            if (a.op == OP_ADJOINT) break;
+            if (a.op == OP_ADVANCE) {
+                for (int n = cur; n < a.arg; ++n) fwd_step(c, n, record);
+                cur = a.arg;
+            } else if (a.op == OP_TAKESHOT) {
+                TRY(snapshot(c, a.arg, cur, 0));
+                c.slot_time[a.arg] = cur;
+            } else {
+                return fail(FWI_EINVAL, "revolve: unexpected action in the first sweep");
+            }
+        }
+        for (int n = cur; n < nt; ++n) fwd_step(c, n, record);
+    } else {
+        const int K = c.po.every;
+        for (int n = 0; n < nt; ++n) {
+            fwd_step(c, n, record);
+            const int t = n + 1;
+            if (K > 0 && t % K == 0 && t <= c.po.ctop - K) TRY(snapshot(c, t / K - 1, t, 0));
+        }
+    }
+    if (record)
+        launch_gather(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
+                      c.gthreads, nt, c.st);
+    HIP_TRY(hipGetLastError());
+    return FWI_OK;
+}
+
+// Adjoint sweep k = nt .. 1 with gradient accumulation; assumes the ring
+// holds the end state of forward_phase.
+int backward_phase(Ctx &c)
+{
+    const int nt = c.p->nt;
+    const uint64_t fs = (uint64_t)c.g.fstride;
+    zero(c.jobs[0].adj, 2 * fs * c.p->nshots, c.st);
+    zero(c.jobs[0].grad, fs * c.p->nshots, c.st);
+    adj_step(c, nt);
+    if (c.po.kind == FWI_CKPT_REVOLVE) {
+        int64_t steps = 0;
+        std::vector<Action> acts = revolve_schedule(nt, c.po.nsnap, &steps);
+        c.slot_time.assign(std::max(c.po.nsnap, 1), -1);
+        size_t i = 0;
+        int cur = 0;
+        for (; i < acts.size() && acts[i].op != OP_ADJOINT; ++i) {
+            if (acts[i].op == OP_ADVANCE) cur = acts[i].arg;
+            else if (acts[i].op == OP_TAKESHOT) c.slot_time[acts[i].arg] = cur;
+        }
+        cur = nt;
+        for (; i < acts.size(); ++i) {
+            const Action &a = acts[i];
+            switch (a.op) {
+            case OP_ADJOINT: adj_step(c, a.arg); break;
+            case OP_ADVANCE:
+                for (int n = cur; n < a.arg; ++n) fwd_step(c, n, false);
+                cur = a.arg;
+                break;
+            case OP_TAKESHOT: TRY(snapshot(c, a.arg, cur, 0)); c.slot_time[a.arg] = cur; break;
+            case OP_RESTORE:
+                if (a.arg < 0 || a.arg >= (int)c.slot_time.size() || c.slot_time[a.arg] < 0)
+                    return fail(FWI_EINVAL, "internal: restore of an empty slot");
+                cur = c.slot_time[a.arg];
+                TRY(snapshot(c, a.arg, cur, 1));
+                break;
+            case OP_RESTART: TRY(snapshot(c, 0, 0, 2)); cur = 0; break;
+            default: return fail(FWI_EINVAL, "revolve: bad action");
+            }
+        }
+    } else {
+        const int K = c.po.every, ctop = c.po.ctop;
+        for (int k = nt - 1; k >= std::max(ctop, 1); --k) adj_step(c, k);
+        for (int base = ctop - K; base >= 0; base -= K) {
+            if (base == 0) TRY(snapshot(c, 0, 0, 2));
+            else TRY(snapshot(c, base / K - 1, base, 1));
+            for (int n = base; n < base + K - 1; ++n) fwd_step(c, n, false);
+            for (int k = base + K - 1; k >= std::max(base, 1); --k) adj_step(c, k);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return FWI_OK;
+}
+
+int fold(Ctx &c, const float *v, float *dv)
+{
+    const Geometry &g = c.g;
+    launch_fold(g.ndim, c.d_jobs, c.p->nshots, g.M, g.gy, g.nz, g.ny, g.nx, g.nb, g.nzm, g.nym,
+                g.nxm, c.f_at(c.L.fold1, true), c.f_at(c.L.fold2, true), v, dv, c.st);
+    HIP_TRY(hipGetLastError());
+    return FWI_OK;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- the ABI
+extern "C" {
+
+const char *fwi_strerror(int status)
+{
+    switch (status) {
+    case FWI_OK: return "ok";
+    case FWI_EINVAL: return "invalid argument";
+    case FWI_ECFL: return "time step above the stability limit";
+    case FWI_EBOUNDS: return "position outside the model grid";
+    case FWI_ENOMEM: return "workspace too small";
+    case FWI_EHIP: return "HIP runtime error";
+    case FWI_ENONFINITE: return "non-finite wavefield or misfit";
+    case FWI_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+const char *fwi_last_error(void) { return g_err; }
+
+int fwi_cfl_limit(int32_t ndim, int32_t order, double *h_cfl_max)
+{
+    if (ndim != 2 && ndim != 3) return fail(FWI_EINVAL, "ndim must be 2 or 3");
+    if (order != 2 && order != 4 && order != 8 && order != 16)
+        return fail(FWI_EINVAL, "order must be 2, 4, 8 or 16");
+    if (!h_cfl_max) return fail(FWI_EINVAL, "NULL output");
+    *h_cfl_max = std::sqrt(4.0 / (ndim * max_symbol(order)));
+    return FWI_OK;
+}
+
+int fwi_workspace_bytes(const fwi_problem *prob, int32_t mode, const fwi_ckpt *ckpt,
+                        uint64_t *h_bytes)
+{
+    if (!h_bytes) return fail(FWI_EINVAL, "NULL output");
+    if (mode < FWI_MODE_FORWARD || mode > FWI_MODE_CKPT_BUF) return fail(FWI_EINVAL, "bad mode");
+    Geometry g;
+    int st = make_geometry(prob, &g);
+    if (st) return st;
+    Policy po;
+    const int m = mode == FWI_MODE_CKPT_BUF ? FWI_MODE_FORWARD_CKPT : mode;
+    st = make_policy(prob, g, m, ckpt, &po);
+    if (st) return st;
+    Layout L;
+    make_layout(prob, g, po, m, &L);
+    *h_bytes = mode == FWI_MODE_CKPT_BUF ? L.ck_total : L.ws_total;
+    return FWI_OK;
+}
+
+int fwi_forward(const fwi_problem *prob, const float *v, const float *src,
+                const int32_t *src_pos, const int32_t *rec_pos, float *traces, void *ws,
+                uint64_t ws_bytes, void *stream)
+{
+    try {
+        Ctx c;
+        int st = prepare(c, prob, FWI_MODE_FORWARD, nullptr, ws, ws_bytes, nullptr, 0, stream);
+        if (st) return st;
+        if (!src || (prob->nrec > 0 && !traces)) return fail(FWI_EINVAL, "NULL input/output array");
+        st = stage(c, v, src, src_pos, rec_pos, prob->nrec > 0 ? traces : nullptr, nullptr, 0);
+        if (st) return st;
+        return forward_phase(c, prob->nrec > 0);
+    } catch (const std::bad_alloc &) {
+        return fail(FWI_EINVAL, "host allocation failed");
+    } catch (...) {
+        return fail(FWI_EINVAL, "internal error");
+    }
+}
+
+int fwi_forward_ckpt(const fwi_problem *prob, const float *v, const float *src,
+                     const int32_t *src_pos, const int32_t *rec_pos, const fwi_ckpt *ckpt,
+                     float *traces, void *ckpt_buf, uint64_t ckpt_bytes, void *ws,
+                     uint64_t ws_bytes, void *stream)
+{
+    try {
+        Ctx c;
+        int st = prepare(c, prob, FWI_MODE_FORWARD_CKPT, ckpt, ws, ws_bytes, ckpt_buf,
+                         ckpt_bytes, stream);
+        if (st) return st;
+        if (!src || (prob->nrec > 0 && !traces)) return fail(FWI_EINVAL, "NULL input/output array");
+        st = stage(c, v, src, src_pos, rec_pos, prob->nrec > 0 ? traces : nullptr, nullptr, 1);
+        if (st) return st;
+        return forward_phase(c, prob->nrec > 0);
+    } catch (const std::bad_alloc &) {
+        return fail(FWI_EINVAL, "host allocation failed");
+    } catch (...) {
+        return fail(FWI_EINVAL, "internal error");
+    }
+}
+
+int fwi_backward(const fwi_problem *prob, const float *v, const float *src,
+                 const int32_t *src_pos, const int32_t *rec_pos, const fwi_ckpt *ckpt,
+                 void *ckpt_buf, uint64_t ckpt_bytes, const float *grad_traces, float *dv,
+                 void *ws, uint64_t ws_bytes, void *stream)
+{
+    try {
+        Ctx c;
+        int st = prepare(c, prob, FWI_MODE_BACKWARD, ckpt, ws, ws_bytes, ckpt_buf, ckpt_bytes,
+                         stream);
+        if (st) return st;
+        if (!src || !dv || (prob->nrec > 0 && !grad_traces))
+            return fail(FWI_EINVAL, "NULL input/output array");
+        st = stage(c, v, src, src_pos, rec_pos, nullptr, grad_traces, 1);
+        if (st) return st;
+        st = backward_phase(c);
+        if (st) return st;
+        return fold(c, v, dv);
+    } catch (const std::bad_alloc &) {
+        return fail(FWI_EINVAL, "host allocation failed");
+    } catch (...) {
+        return fail(FWI_EINVAL, "internal error");
+    }
+}
+
+int fwi_gradient(const fwi_problem *prob, const float *v, const float *src,
+                 const int32_t *src_pos, const int32_t *rec_pos, const float *obs,
+                 const fwi_ckpt *ckpt, double *h_misfit, float *dv, float *traces_or_null,
+                 void *ws, uint64_t ws_bytes, void *stream)
+{
+    try {
+        Ctx c;
+        int st = prepare(c, prob, FWI_MODE_GRADIENT, ckpt, ws, ws_bytes, nullptr, 0, stream);
+        if (st) return st;
+        if (!src || !dv || !h_misfit || (prob->nrec > 0 && !obs))
+            return fail(FWI_EINVAL, "NULL input/output array");
+        float *res = c.f_at(c.L.res, true);
+        float *rec = traces_or_null ? traces_or_null : res;
+        st = stage(c, v, src, src_pos, rec_pos, prob->nrec > 0 ? rec : nullptr, res, 1);
+        if (st) return st;
+        st = forward_phase(c, prob->nrec > 0);
+        if (st) return st;
+        double *d_mis = reinterpret_cast<double *>(c.ws + c.L.misfit);
+        const int64_t ntr = (int64_t)prob->nshots * prob->nt * prob->nrec;
+        if (ntr > 0) {
+            launch_misfit(rec, obs, res, ntr, reinterpret_cast<double *>(c.ws + c.L.partial),
+                          d_mis, c.st);
+        } else {
+            launch_fill(reinterpret_cast<float *>(d_mis), 4, 0.f, c.st);   // 16 B slot
+        }
+        HIP_TRY(hipGetLastError());
+        st = backward_phase(c);
+        if (st) return st;
+        st = fold(c, v, dv);
+        if (st) return st;
+        HIP_TRY(hipMemcpyAsync(h_misfit, d_mis, sizeof(double), hipMemcpyDeviceToHost, c.st));
+        HIP_TRY(hipStreamSynchronize(c.st));
+        if (!std::isfinite(*h_misfit)) return fail(FWI_ENONFINITE, "misfit is not finite");
+        return FWI_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FWI_EINVAL, "host allocation failed");
+    } catch (...) {
+        return fail(FWI_EINVAL, "internal error");
+    }
+}
+
+int fwi_velocity_range(const float *v, int64_t n, float *h_vmin, float *h_vmax, void *ws,
+                       uint64_t ws_bytes, void *stream)
+{
+    if (!v || n < 1 || !h_vmin || !h_vmax || !ws) return fail(FWI_EINVAL, "bad argument");
+    const int B = vstats_blocks();
+    if (ws_bytes < 4096 || ws_bytes < sizeof(float) * 3ull * B)
+        return fail(FWI_ENOMEM, "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float *d = static_cast<float *>(ws);
+    launch_vstats(v, n, d, st);
+    HIP_TRY(hipGetLastError());
+    std::vector<float> h(3 * (size_t)B);
+    HIP_TRY(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float lo = INFINITY, hi = -INFINITY, bad = 0.f;
+    for (int i = 0; i < B; ++i) {
+        lo = std::min(lo, h[i]);
+        hi = std::max(hi, h[B + i]);
+        bad += h[2 * B + i];
+    }
+    if (bad > 0.f) return fail(FWI_EINVAL, "velocity has non-finite values");
+    *h_vmin = lo;
+    *h_vmax = hi;
+    return FWI_OK;
+}
+
+int fwi_revolve_schedule(int32_t nsteps, int32_t slots, int32_t *h_actions, int64_t cap,
+                         int64_t *h_count, int64_t *h_forward_steps)
+{
+    if (nsteps < 1 || slots < 0) return fail(FWI_EINVAL, "nsteps >= 1 and slots >= 0 required");
+    if (!h_count || !h_forward_steps) return fail(FWI_EINVAL, "NULL output");
+    try {
+        int64_t steps = 0;
+        std::vector<Action> acts = revolve_schedule(nsteps, slots, &steps);
+        *h_count = (int64_t)acts.size();
+        *h_forward_steps = steps + 1;   // plus the recording sweep's last step
+        if (h_actions)
+            for (int64_t i = 0; i < cap && i < (int64_t)acts.size(); ++i) {
+                h_actions[2 * i] = acts[i].op;
+                h_actions[2 * i + 1] = acts[i].arg;
+            }
+        return FWI_OK;
+    } catch (...) {
+        return fail(FWI_EINVAL, "internal error");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+"""Host-side checks of libfwi.so that need no GPU.
+
+The library loads, exports every entry point include/fwi.h declares, and its
+host-only logic is right: argument validation happens before any device
+call, workspace sizing, the stability limit, and the revolve checkpointing
+schedule (optimal step count against a brute-force dynamic programme and the
+closed-form binomial bound; validity by replaying it on a fake executor).
+"""
+import ctypes
+import functools
+import math
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_1912_08063_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _prob(**kw):
+    p = _lib.FwiProblem()
+    p.ndim = kw.get("ndim", 2)
+    for i, n in enumerate(kw.get("shape", (64, 80))):
+        p.shape[i] = n
+    p.dx = kw.get("dx", 10.0)
+    p.dt = kw.get("dt", 1e-3)
+    p.nt = kw.get("nt", 100)
+    p.order = kw.get("order", 8)
+    p.nsponge = kw.get("nsponge", 10)
+    p.eta_max = kw.get("eta_max", 100.0)
+    p.nshots = kw.get("nshots", 1)
+    p.nrec = kw.get("nrec", 5)
+    return p
+
+
+def test_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "fwi.h")).read()
+    declared = set(re.findall(r"^(?:int|const char \*)\s*(fwi_\w+)\(", header, re.M))
+    assert declared == set(_lib.EXPORTS)
+    lib = _lib.load()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_last_error():
+    lib = _lib.load()
+    assert lib.fwi_strerror(0) == b"ok"
+    assert b"stability" in lib.fwi_strerror(_lib.FWI_ECFL)
+    assert lib.fwi_strerror(12345) == b"unknown status"
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("order", [2, 4, 8, 16])
+def test_cfl_limit_matches_oracle(ndim, order):
+    assert abs(_lib.fwi_cfl_limit(ndim, order) - oracle.cfl_limit(ndim, order)) < 1e-6
+
+
+@pytest.mark.parametrize("bad", [dict(ndim=4), dict(order=6), dict(dx=0.0), dict(dt=-1.0),
+                                 dict(nt=0), dict(nsponge=-1), dict(eta_max=-1.0),
+                                 dict(nshots=0), dict(nrec=-2), dict(shape=(0, 10))])
+def test_invalid_problems_rejected_before_any_device_call(bad):
+    p = _prob(**bad)
+    with pytest.raises(_lib.FwiError) as e:
+        _lib.fwi_workspace_bytes(p, _lib.MODE_FORWARD)
+    assert e.value.status == _lib.FWI_EINVAL
+    lib = _lib.load()
+    # the entry points validate the problem before touching any pointer
+    st = lib.fwi_forward(ctypes.byref(p), None, None, None, None, None, None, 0, None)
+    assert st == _lib.FWI_EINVAL
+
+
+def test_workspace_too_small_is_enomem_without_device():
+    p = _prob()
+    lib = _lib.load()
+    need = _lib.fwi_workspace_bytes(p, _lib.MODE_FORWARD)
+    st = lib.fwi_forward(ctypes.byref(p), None, None, None, None, None, 256, need - 1, None)
+    assert st == _lib.FWI_ENOMEM
+
+
+def test_workspace_sizes_grow_with_the_policy():
+    p = _prob(nt=300, nshots=4)
+    f = _lib.fwi_workspace_bytes(p, _lib.MODE_FORWARD)
+    ck_all = _lib.FwiCkpt(kind=_lib.CKPT_ALL)
+    ck_e = _lib.FwiCkpt(kind=_lib.CKPT_EVERY, every=30)
+    ck_r = _lib.FwiCkpt(kind=_lib.CKPT_REVOLVE, slots=5)
+    g_all = _lib.fwi_workspace_bytes(p, _lib.MODE_GRADIENT, ck_all)
+    g_e = _lib.fwi_workspace_bytes(p, _lib.MODE_GRADIENT, ck_e)
+    g_r = _lib.fwi_workspace_bytes(p, _lib.MODE_GRADIENT, ck_r)
+    assert f < g_r < g_e < g_all
+    # a field is at least the padded grid with its frame
+    cells = (64 + 20 + 8) * (80 + 20 + 8)
+    assert _lib.fwi_workspace_bytes(p, _lib.MODE_CKPT_BUF, ck_all) >= 301 * 4 * 4 * cells
+
+
+# ------------------------------------------------------------------ revolve
+@functools.lru_cache(maxsize=None)
+def _dp(l, s):
+    """Brute force: minimal forward steps to visit states l-1..0 in reverse,
+    state 0 held in one of s snapshots."""
+    if l <= 1:
+        return 0
+    if s <= 1:
+        return l * (l - 1) // 2
+    return min(m + _dp(l - m, s - 1) + _dp(m, s) for m in range(1, l))
+
+
+def _closed_form(l, s):
+    beta = lambda s_, r_: math.comb(s_ + r_, s_) if r_ >= 0 else 0
+    r = 0
+    while beta(s, r) < l:
+        r += 1
+    return r * l - beta(s + 1, r - 1)
+
+
+def test_revolve_closed_form_matches_brute_force():
+    for l in range(1, 61):
+        for s in range(1, 7):
+            assert _dp(l, s) == _closed_form(l, s), (l, s)
+
+
+def _replay(nsteps, slots, acts):
+    """Fake executor: replays a schedule and checks that every adjoint visit
+    sees the right forward state, in the order nsteps-1 .. 1."""
+    cur = 0
+    held = {}
+    visits = []
+    steps = 0
+    started = False
+    for op, arg in acts:
+        if op == _lib.OP_ADVANCE:
+            assert arg > cur
+            steps += arg - cur
+            cur = arg
+        elif op == _lib.OP_TAKESHOT:
+            assert 0 <= arg < slots
+            held[arg] = cur
+        elif op == _lib.OP_RESTORE:
+            assert arg in held
+            cur = held[arg]
+        elif op == _lib.OP_RESTART:
+            cur = 0
+        elif op == _lib.OP_ADJOINT:
+            assert arg == cur
+            visits.append(arg)
+            started = True
+        else:
+            raise AssertionError(op)
+    assert visits == list(range(nsteps - 1, 0, -1))
+    return steps
+
+
+@pytest.mark.parametrize("nsteps,slots", [(1, 0), (2, 0), (7, 0), (10, 1), (10, 3), (37, 2),
+                                          (60, 4), (100, 7), (200, 10), (64, 70)])
+def test_revolve_schedule_is_valid_and_optimal(nsteps, slots):
+    acts, fwd = _lib.fwi_revolve_schedule(nsteps, slots)
+    steps = _replay(nsteps, slots, acts)
+    assert fwd == steps + 1   # plus the recording sweep's last step
+    # slots physical snapshots plus the free zero state
+    assert steps == _dp(nsteps, slots + 1) == _closed_form(nsteps, slots + 1)
+
+
+def test_revolve_large_schedule_matches_bound():
+    # a 3000-step reversal with 52 snapshots (state 0 stored) costs 7515 steps;
+    # with the zero state free the same 52 slots act as 53 snapshots
+    assert _closed_form(3000, 52) == 7515
+    _, fwd = _lib.fwi_revolve_schedule(3000, 51, with_actions=False)
+    assert fwd - 1 == 7515
+    acts, fwd = _lib.fwi_revolve_schedule(3000, 52)
+    assert _replay(3000, 52, acts) == fwd - 1 == _closed_form(3000, 53)

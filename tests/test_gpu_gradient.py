@@ -1,0 +1,128 @@
+"""Misfit and gradient: HIP library vs the FP64 oracle; checkpoint invariance;
+the autograd.Function against fwi_gradient.
+
+Tolerances: relative L2 <= 1e-3 on dv, relative 1e-4 on traces and 1e-3 on
+the misfit.  Every checkpoint policy must give bitwise the same dv, since all
+of them recompute exactly the same forward levels with the same kernels.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import (cfg, dev, f32, gpu_gradient, inputs, oracle_forward, oracle_gradient,
+                        rel_l2)
+from paper_1912_08063_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(P, smooth=3.0):
+    P = f32(P)
+    obs = np.asarray(oracle_forward(P), dtype=np.float32).astype(np.float64)
+    v0 = np.asarray(wl.smooth(P.v, smooth), dtype=np.float32).astype(np.float64)
+    return P, obs, v0
+
+
+def _check(P, obs, v0, ckpt="all"):
+    mis_o, dv_o = oracle_gradient(P, v0, obs)
+    mis_g, dv_g, tr_g = gpu_gradient(P, v0, obs, ckpt)
+    assert rel_l2(tr_g, oracle_forward(P, v0)) <= 1e-4
+    assert abs(mis_g - mis_o) <= 1e-3 * abs(mis_o), (mis_g, mis_o)
+    assert rel_l2(dv_g, dv_o) <= 1e-3, rel_l2(dv_g, dv_o)
+    return dv_g
+
+
+@pytest.mark.parametrize("order", [8, 16])
+def test_gradient_2d(order):
+    P, obs, v0 = _setup(wl.small_2d(nz=48, nx=131, nt=220, order=order, nshots=2, nrec=40))
+    _check(P, obs, v0, "every:25")
+
+
+def test_gradient_3d():
+    P, obs, v0 = _setup(wl.small_3d(shape=(26, 22, 75), nt=90, nshots=2, nrec=30), 1.5)
+    _check(P, obs, v0, "revolve:4")
+
+
+def test_gradient_duplicate_receivers_and_sponge_edges():
+    P = wl.small_2d(nz=30, nx=70, nt=120, nrec=8, nb=9)
+    P.rec_pos[0, 4:] = P.rec_pos[0, 0]
+    P.src_pos[0] = [0, 69]
+    P, obs, v0 = _setup(P)
+    _check(P, obs, v0, "all")
+
+
+def test_checkpoint_policies_bitwise_identical():
+    P, obs, v0 = _setup(wl.small_2d(nz=40, nx=100, nt=97, nshots=3, nrec=20))
+    ref_mis, ref_dv, ref_tr = gpu_gradient(P, v0, obs, "all")
+    for ck in ["every:1", "every:7", "every:50", "every:97", "every:500", "revolve:0",
+               "revolve:1", "revolve:3", "revolve:10", "revolve:200"]:
+        mis, dv, tr = gpu_gradient(P, v0, obs, ck)
+        assert mis == ref_mis, ck
+        assert np.array_equal(tr, ref_tr), ck
+        assert np.array_equal(dv, ref_dv), ck
+
+
+def test_3d_checkpoint_policies_bitwise_identical():
+    P, obs, v0 = _setup(wl.small_3d(shape=(20, 18, 66), nt=41, nrec=12), 1.5)
+    _, ref, _ = gpu_gradient(P, v0, obs, "all")
+    for ck in ["every:6", "revolve:2"]:
+        assert np.array_equal(gpu_gradient(P, v0, obs, ck)[1], ref), ck
+
+
+def test_zero_residual_gives_zero_gradient():
+    import torch
+    from paper_1912_08063_amd import api
+    P = f32(wl.small_2d(nz=30, nx=80, nt=60, nrec=10))
+    v, w, s, r = inputs(P)
+    obs = api.forward(v, w, s, r, cfg(P))
+    mis, dv = api.gradient(v, obs, w, s, r, cfg(P, "every:9"))
+    torch.cuda.synchronize()
+    assert mis == 0.0 and float(dv.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("ckpt", ["every:11", "revolve:3"])
+def test_autograd_function_matches_fwi_gradient(ckpt):
+    import torch
+    from paper_1912_08063_amd.autograd import FWIForward
+    P, obs, v0 = _setup(wl.small_2d(nz=40, nx=90, nt=130, nshots=2, nrec=21))
+    mis_g, dv_g, _ = gpu_gradient(P, v0, obs, ckpt)
+    vt, w, s, r = inputs(P, v0)
+    vt.requires_grad_(True)
+    tr = FWIForward.apply(vt, w, s, r, cfg(P, ckpt))
+    loss = ((tr - dev(obs, torch.float32)) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    g = vt.grad.cpu().numpy().astype(np.float64)
+    assert rel_l2(g, dv_g) <= 1e-6
+    assert abs(float(loss) - mis_g) <= 1e-5 * mis_g
+    # a second backward through consumed checkpoints must fail loudly
+    tr2 = FWIForward.apply(vt, w, s, r, cfg(P, ckpt))
+    l2 = tr2.sum()
+    l2.backward(retain_graph=True)
+    with pytest.raises(RuntimeError):
+        l2.backward()
+
+
+def test_autograd_matches_central_differences():
+    """<dv, dir> from the autograd backward against central differences of the
+    GPU forward misfit in fp64 sums (h chosen for fp32 traces)."""
+    import torch
+    from paper_1912_08063_amd import api
+    from paper_1912_08063_amd.autograd import FWIForward
+    P, obs, v0 = _setup(wl.small_2d(nz=40, nx=90, nt=160, nrec=30), 4.0)
+    rng = np.random.default_rng(0)
+    direction = wl.smooth(rng.standard_normal(v0.shape), 2.0)
+    direction /= np.abs(direction).max()
+    vt, w, s, r = inputs(P, v0)
+    vt.requires_grad_(True)
+    tr = FWIForward.apply(vt, w, s, r, cfg(P, "every:20"))
+    ((tr - dev(obs, torch.float32)) ** 2).sum().backward()
+    an = float(np.sum(vt.grad.cpu().numpy().astype(np.float64) * direction))
+
+    def phi(v):
+        vv, _, _, _ = inputs(P, v)
+        d = api.forward(vv, w, s, r, cfg(P)).cpu().numpy().astype(np.float64)
+        return float(np.sum((d - obs) ** 2))
+
+    h = 2.0   # m/s
+    fd = (phi(v0 + h * direction) - phi(v0 - h * direction)) / (2 * h)
+    assert abs(fd - an) <= 1e-2 * abs(an), (fd, an)
