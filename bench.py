@@ -53,6 +53,8 @@ def main():
     ap.add_argument("--nt", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
+                    help="only time a plain device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (got --gpus %d); the multi-GPU "
@@ -65,6 +67,25 @@ def main():
     from paper_1912_08063_amd import api, workloads as wl
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        n = int(args.calibrate_copy * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n,
+                          "ms_per_copy": ms, "GBps_read_plus_write": 8 * n / ms / 1e6}),
+              flush=True)
+        return
     log("generating workload")
     P = wl.c2(nt=args.nt)
     t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)

@@ -84,17 +84,44 @@ __device__ __forceinline__ void gather_block(const Job *__restrict__ J, int r, i
     J->traces[(int64_t)(n - 1) * J->nrec + r] = cur[J->rec_off[r]];
 }
 
+// Sponge factors from the squared depth d2 = sum_a d_a^2 into the sponge:
+// eta dt = eta_dt * d2, alpha = 1/(1 + eta dt), beta = (1 - eta dt) alpha.
+// out = alpha * val - beta * prev, written as alpha * (val - (1 - e) prev).
+__device__ __forceinline__ float leapfrog(float val, float prev, int d2, float eta_dt)
+{
+    if (d2 == 0) return val - prev;
+    const float e = eta_dt * (float)d2;
+    return __builtin_amdgcn_rcpf(1.f + e) * fmaf(-(1.f - e), prev, val);
+}
+
+// Plane of a field: element (z, row, col) is at base[(z + M) * plane + row_offset].
+// The plane base is uniform across the block (scalar registers); per-thread
+// offsets within a plane are 32-bit, so every load is base + 32-bit offset.
+__device__ __forceinline__ const float *plane_ptr(const float *f, int zmem, int64_t plane)
+{
+    return f + (int64_t)zmem * plane;
+}
+
 // --------------------------------------------------------------- 3-D step
+// One block: 4 wavefronts, a 64 (x) x 16 (y) tile, marching a chunk of z.
+// Per plane z: the LDS buffer (z & 1) holds plane z of the propagated field
+// with an M-cell halo; registers hold the z-queue (planes z-M .. z+M, in a
+// ring indexed by the unrolled phase k, so no register moves), kappa' and
+// the previous level.  While plane z is computed, plane z+1 is already being
+// loaded (the next queue front, kappa', previous level, halos), and written
+// to the other LDS buffer afterwards: one barrier per plane.
 template <int M, bool ADJ>
 __global__ __launch_bounds__(256) void k_step3d(const Job *__restrict__ jobs,
                                                 const int *__restrict__ prefix, int njobs,
                                                 int step, int ttiles, int remap)
 {
     constexpr int TX = kTileX, RY = kRowsPerWave, TY = kTileY;
-    constexpr int LX = TX + 2 * M, LY = TY + 2 * M, Q = 2 * M + 1;
+    constexpr int LX = TX + 2 * M, LY = TY + 2 * M, Q = 2 * M + 1, LS = LY * LX;
+    constexpr int NYH = (2 * M * TX + 255) / 256;   // y-halo cells per thread
+    constexpr int NXH = (TY * 2 * M + 255) / 256;   // x-halo cells per thread
     constexpr Weights<M> W{};
-    __shared__ float sp[LY * LX];
-    __shared__ float sf[ADJ ? LY * LX : 1];
+    __shared__ float sp[2 * LS];
+    __shared__ float sf[ADJ ? 2 * LS : 1];
 
     const int tid = threadIdx.x;
     int b = blockIdx.x;
@@ -121,13 +148,12 @@ __global__ __launch_bounds__(256) void k_step3d(const Job *__restrict__ jobs,
     const int tz = local / J->nty;
     const int z0 = tz * J->zc, z1 = min(z0 + J->zc, nz);
 
-    // field levels: forward p^n -> p^{n+1}; adjoint psi^{k+1} -> psi^k
     const float *cur, *prv;
     float *out;
     const float *fwd = nullptr;
     float *grad = nullptr;
     bool accum = false;
-    if (ADJ) {
+    if constexpr (ADJ) {
         cur = J->adj + (int64_t)((n + 1) & 1) * fstride;
         prv = J->adj + (int64_t)(n & 1) * fstride;
         out = J->adj + (int64_t)(n & 1) * fstride;
@@ -142,140 +168,230 @@ __global__ __launch_bounds__(256) void k_step3d(const Job *__restrict__ jobs,
     const float *kap = J->kappa;
     const float eta_dt = J->eta_dt;
 
+    // ---- per-thread geometry (loop invariant)
     const int lane = tid & 63, wv = tid >> 6;
     const int col = tx * TX + lane;   // memory column
     const int x = col - M;            // padded-grid x
     const bool ax = x >= 0 && x < nx;
-    int yy[RY];
     bool act[RY];
-    int64_t roff[RY];
-    int dy2[RY];
+    uint32_t roff[RY];
+    int dxy2[RY];
     const int dxs = sponge_depth(x, nx, nb);
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
-        yy[i] = ty * TY + wv * RY + i;
-        act[i] = ax && yy[i] < ny;
-        roff[i] = (int64_t)(yy[i] + M) * pitch + col;
-        const int d = sponge_depth(yy[i], ny, nb);
-        dy2[i] = d * d + dxs * dxs;
+        const int yy = ty * TY + wv * RY + i;
+        act[i] = ax && yy < ny;
+        roff[i] = (uint32_t)((yy + M) * pitch + col);
+        const int d = sponge_depth(yy, ny, nb);
+        dxy2[i] = d * d + dxs * dxs;
     }
+    uint32_t hyo[NYH], hxo[NXH];
+    bool hyv[NYH], hxv[NXH];
+    int hyl[NYH], hxl[NXH];
+#pragma unroll
+    for (int q = 0; q < NYH; ++q) {   // rows above and below the tile
+        const int h = tid + 256 * q;
+        const int r = (h / TX) % (2 * M), c = h % TX;
+        const int ly = r < M ? r : r + TY;
+        const int yg = ty * TY - M + ly;
+        hyv[q] = h < 2 * M * TX && yg < ny + M;
+        hyo[q] = (uint32_t)((yg + M) * pitch + tx * TX + c);
+        hyl[q] = h < 2 * M * TX ? ly * LX + M + c : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < NXH; ++q) {   // columns left and right of the tile
+        const int h = tid + 256 * q;
+        const int r = (h / (2 * M)) % TY, c = h % (2 * M);
+        const int lc = c < M ? c : c + TX;
+        const int cm = tx * TX - M + lc;
+        const int yg = ty * TY + r;
+        hxv[q] = h < TY * 2 * M && cm >= 0 && cm < pitch && yg < ny + M;
+        hxo[q] = (uint32_t)((yg + M) * pitch + cm);
+        hxl[q] = h < TY * 2 * M ? (M + r) * LX + lc : -1;
+    }
+    // source (forward): the block that owns it adds it at its plane
+    const bool src_blk = !ADJ && J->src_x >= tx * TX - M && J->src_x < tx * TX - M + TX &&
+                         J->src_y >= ty * TY && J->src_y < ty * TY + TY && J->src_z >= z0 &&
+                         J->src_z < z1;
     float srcv = 0.f;
-    int src_lrow = -1;
-    if (!ADJ && J->src_z >= z0 && J->src_z < z1 && J->src_x == x) {
+    int src_row = -1;
+    if (src_blk && J->src_x == x) {
         const int r = J->src_y - (ty * TY + wv * RY);
-        if (r >= 0 && r < RY) { src_lrow = r; srcv = J->src_scale * J->wavelet[n]; }
+        if (r >= 0 && r < RY) { src_row = r; srcv = J->src_scale * J->wavelet[n]; }
     }
 
+    // ---- prologue: queue slots 0..2M hold planes z0-M .. z0+M; plane z0 in LDS
     float q[RY][Q];
     float f[ADJ ? RY : 1][ADJ ? Q : 1];
 #pragma unroll
-    for (int s = 0; s < 2 * M; ++s) {
-        const int64_t po = (int64_t)(z0 + s) * plane;   // plane z0 - M + s
+    for (int s = 0; s < Q; ++s) {
+        const float *pc = plane_ptr(cur, z0 + s, plane);   // grid plane z0 - M + s
+        const float *pf = ADJ ? plane_ptr(fwd, z0 + s, plane) : nullptr;
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            q[i][s] = act[i] ? cur[po + roff[i]] : 0.f;
-            if constexpr (ADJ) f[i][s] = act[i] ? fwd[po + roff[i]] : 0.f;
+            q[i][s] = act[i] ? pc[roff[i]] : 0.f;
+            if constexpr (ADJ) f[i][s] = act[i] ? pf[roff[i]] : 0.f;
         }
     }
+    float kv[RY], pv[RY], gv[ADJ ? RY : 1];
+    {
+        const float *pk = plane_ptr(kap, z0 + M, plane);
+        const float *pp = plane_ptr(prv, z0 + M, plane);
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            kv[i] = act[i] ? pk[roff[i]] : 0.f;
+            pv[i] = act[i] ? pp[roff[i]] : 0.f;
+            if constexpr (ADJ) gv[i] = act[i] && accum ? plane_ptr(grad, z0 + M, plane)[roff[i]] : 0.f;
+        }
+        const float *pc = plane_ptr(cur, z0 + M, plane);
+        const float *pf = ADJ ? plane_ptr(fwd, z0 + M, plane) : nullptr;
+        float *L = sp + (z0 & 1) * LS;
+        float *LF = ADJ ? sf + (z0 & 1) * LS : nullptr;
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            L[(M + wv * RY + i) * LX + M + lane] = q[i][M];
+            if constexpr (ADJ) LF[(M + wv * RY + i) * LX + M + lane] = f[i][M];
+        }
+#pragma unroll
+        for (int h = 0; h < NYH; ++h)
+            if (hyl[h] >= 0) {
+                L[hyl[h]] = hyv[h] ? pc[hyo[h]] : 0.f;
+                if constexpr (ADJ) LF[hyl[h]] = hyv[h] ? pf[hyo[h]] : 0.f;
+            }
+#pragma unroll
+        for (int h = 0; h < NXH; ++h)
+            if (hxl[h] >= 0) {
+                L[hxl[h]] = hxv[h] ? pc[hxo[h]] : 0.f;
+                if constexpr (ADJ) LF[hxl[h]] = hxv[h] ? pf[hxo[h]] : 0.f;
+            }
+    }
+    __syncthreads();
 
-    for (int z = z0; z < z1; ++z) {
-        const int64_t pz = (int64_t)(z + M) * plane;   // plane z
-        const int64_t pf = pz + (int64_t)M * plane;    // plane z + M
-        float kv[RY], pv[RY];
+    for (int zb = z0; zb < z1; zb += Q) {
 #pragma unroll
-        for (int i = 0; i < RY; ++i) {
-            q[i][2 * M] = act[i] ? cur[pf + roff[i]] : 0.f;
-            if constexpr (ADJ) f[i][2 * M] = act[i] ? fwd[pf + roff[i]] : 0.f;
-            kv[i] = act[i] ? kap[pz + roff[i]] : 0.f;
-            pv[i] = act[i] ? prv[pz + roff[i]] : 0.f;
-        }
-        // stage plane z with its halo in LDS
+        for (int k = 0; k < Q; ++k) {
+            const int z = zb + k;
+            if (z < z1) {
+            const bool more = z + 1 < z1;
+            // ---- prefetch plane z+1 (queue front z+1+M, kappa', previous level, halos)
+            float nq[RY], nk[RY], np[RY], nhy[NYH], nhx[NXH];
+            float nfq[ADJ ? RY : 1], ng[ADJ ? RY : 1], nfy[ADJ ? NYH : 1], nfx[ADJ ? NXH : 1];
+            if (more) {
+                const float *pq = plane_ptr(cur, z + 1 + 2 * M, plane);
+                const float *pk = plane_ptr(kap, z + 1 + M, plane);
+                const float *pp = plane_ptr(prv, z + 1 + M, plane);
+                const float *ph = plane_ptr(cur, z + 1 + M, plane);
 #pragma unroll
-        for (int i = 0; i < RY; ++i) {
-            sp[(M + wv * RY + i) * LX + M + lane] = q[i][M];
-            if constexpr (ADJ) sf[(M + wv * RY + i) * LX + M + lane] = f[i][M];
-        }
-        for (int h = tid; h < 2 * M * TX; h += 256) {   // rows above and below
-            const int r = h / TX, c = h % TX;
-            const int ly = r < M ? r : r + TY;
-            const int yg = ty * TY - M + ly;
-            float a = 0.f, bq = 0.f;
-            if (yg < ny + M) {
-                const int64_t o = pz + (int64_t)(yg + M) * pitch + tx * TX + c;
-                a = cur[o];
-                if constexpr (ADJ) bq = fwd[o];
-            }
-            sp[ly * LX + M + c] = a;
-            if constexpr (ADJ) sf[ly * LX + M + c] = bq;
-        }
-        for (int h = tid; h < TY * 2 * M; h += 256) {   // columns left and right
-            const int r = h / (2 * M), c = h % (2 * M);
-            const int lc = c < M ? c : c + TX;
-            const int cm = tx * TX - M + lc;
-            const int yg = ty * TY + r;
-            float a = 0.f, bq = 0.f;
-            if (cm >= 0 && cm < pitch && yg < ny + M) {
-                const int64_t o = pz + (int64_t)(yg + M) * pitch + cm;
-                a = cur[o];
-                if constexpr (ADJ) bq = fwd[o];
-            }
-            sp[(M + r) * LX + lc] = a;
-            if constexpr (ADJ) sf[(M + r) * LX + lc] = bq;
-        }
-        __syncthreads();
-
-        const int dz = sponge_depth(z, nz, nb);
-#pragma unroll
-        for (int i = 0; i < RY; ++i) {
-            if (!act[i]) continue;
-            const int ly = M + wv * RY + i, lx = M + lane;
-            const float pc = q[i][M];
-            float acc = 0.f;
-#pragma unroll
-            for (int m = M; m >= 1; --m) {
-                const float d = ((sp[ly * LX + lx + m] - pc) + (sp[ly * LX + lx - m] - pc)) +
-                                ((sp[(ly + m) * LX + lx] - pc) + (sp[(ly - m) * LX + lx] - pc)) +
-                                ((q[i][M + m] - pc) + (q[i][M - m] - pc));
-                acc = fmaf(W.c[m], d, acc);
-            }
-            float val = fmaf(kv[i], acc, 2.f * pc);
-            if (!ADJ && i == src_lrow && z == J->src_z) val += srcv;
-            const int d2 = dy2[i] + dz * dz;
-            float o;
-            if (d2 == 0) {
-                o = val - pv[i];
-            } else {
-                const float e = eta_dt * (float)d2;
-                const float a = 1.f / (1.f + e);
-                o = a * val - (1.f - e) * a * pv[i];
-            }
-            out[pz + roff[i]] = o;
-            if constexpr (ADJ) if (accum) {
-                const float fc = f[i][M];
-                float lf = 0.f;
-#pragma unroll
-                for (int m = M; m >= 1; --m) {
-                    const float d = ((sf[ly * LX + lx + m] - fc) + (sf[ly * LX + lx - m] - fc)) +
-                                    ((sf[(ly + m) * LX + lx] - fc) + (sf[(ly - m) * LX + lx] - fc)) +
-                                    ((f[i][M + m] - fc) + (f[i][M - m] - fc));
-                    lf = fmaf(W.c[m], d, lf);
+                for (int i = 0; i < RY; ++i) {
+                    nq[i] = act[i] ? pq[roff[i]] : 0.f;
+                    nk[i] = act[i] ? pk[roff[i]] : 0.f;
+                    np[i] = act[i] ? pp[roff[i]] : 0.f;
                 }
-                grad[pz + roff[i]] += pc * lf;
-            }
-        }
-        __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 2 * M; ++s) {
+                for (int h = 0; h < NYH; ++h) nhy[h] = hyv[h] ? ph[hyo[h]] : 0.f;
+#pragma unroll
+                for (int h = 0; h < NXH; ++h) nhx[h] = hxv[h] ? ph[hxo[h]] : 0.f;
+                if constexpr (ADJ) {
+                    const float *fq = plane_ptr(fwd, z + 1 + 2 * M, plane);
+                    const float *fh = plane_ptr(fwd, z + 1 + M, plane);
+                    const float *pg = plane_ptr(grad, z + 1 + M, plane);
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) {
+                        nfq[i] = act[i] ? fq[roff[i]] : 0.f;
+                        ng[i] = act[i] && accum ? pg[roff[i]] : 0.f;
+                    }
+#pragma unroll
+                    for (int h = 0; h < NYH; ++h) nfy[h] = hyv[h] ? fh[hyo[h]] : 0.f;
+#pragma unroll
+                    for (int h = 0; h < NXH; ++h) nfx[h] = hxv[h] ? fh[hxo[h]] : 0.f;
+                }
+            }
+            // ---- plane z
+            const float *L = sp + (z & 1) * LS;
+            const float *LF = ADJ ? sf + (z & 1) * LS : nullptr;
+            float *po = const_cast<float *>(plane_ptr(out, z + M, plane));
+            float *pg = ADJ ? const_cast<float *>(plane_ptr(grad, z + M, plane)) : nullptr;
+            const int dz = sponge_depth(z, nz, nb);
+            float res[RY];
 #pragma unroll
             for (int i = 0; i < RY; ++i) {
-                q[i][s] = q[i][s + 1];
-                if constexpr (ADJ) f[i][s] = f[i][s + 1];
+                const int ly = M + wv * RY + i, lx = M + lane;
+                const float pc = q[i][(k + M) % Q];
+                float acc = 0.f;
+#pragma unroll
+                for (int m = M; m >= 1; --m) {
+                    const float d = ((L[ly * LX + lx + m] - pc) + (L[ly * LX + lx - m] - pc)) +
+                                    ((L[(ly + m) * LX + lx] - pc) + (L[(ly - m) * LX + lx] - pc)) +
+                                    ((q[i][(k + M + m) % Q] - pc) + (q[i][(k + M - m) % Q] - pc));
+                    acc = fmaf(W.c[m], d, acc);
+                }
+                res[i] = fmaf(kv[i], acc, 2.f * pc);
+            }
+            if (src_blk && z == J->src_z) {
+#pragma unroll
+                for (int i = 0; i < RY; ++i) res[i] += i == src_row ? srcv : 0.f;
+            }
+#pragma unroll
+            for (int i = 0; i < RY; ++i)
+                if (act[i]) po[roff[i]] = leapfrog(res[i], pv[i], dxy2[i] + dz * dz, eta_dt);
+            if constexpr (ADJ) {
+                if (accum) {
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) {
+                        const int ly = M + wv * RY + i, lx = M + lane;
+                        const float fc = f[i][(k + M) % Q];
+                        float lf = 0.f;
+#pragma unroll
+                        for (int m = M; m >= 1; --m) {
+                            const float d =
+                                ((LF[ly * LX + lx + m] - fc) + (LF[ly * LX + lx - m] - fc)) +
+                                ((LF[(ly + m) * LX + lx] - fc) + (LF[(ly - m) * LX + lx] - fc)) +
+                                ((f[i][(k + M + m) % Q] - fc) + (f[i][(k + M - m) % Q] - fc));
+                            lf = fmaf(W.c[m], d, lf);
+                        }
+                        if (act[i]) pg[roff[i]] = fmaf(q[i][(k + M) % Q], lf, gv[i]);
+                    }
+                }
+            }
+            // ---- rotate to plane z+1 and stage it in the other LDS buffer
+            if (more) {
+                float *Ln = sp + ((z + 1) & 1) * LS;
+                float *LFn = ADJ ? sf + ((z + 1) & 1) * LS : nullptr;
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    q[i][k] = nq[i];   // slot k held plane z - M
+                    kv[i] = nk[i];
+                    pv[i] = np[i];
+                    Ln[(M + wv * RY + i) * LX + M + lane] = q[i][(k + M + 1) % Q];
+                    if constexpr (ADJ) {
+                        f[i][k] = nfq[i];
+                        gv[i] = ng[i];
+                        LFn[(M + wv * RY + i) * LX + M + lane] = f[i][(k + M + 1) % Q];
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < NYH; ++h)
+                    if (hyl[h] >= 0) {
+                        Ln[hyl[h]] = nhy[h];
+                        if constexpr (ADJ) LFn[hyl[h]] = nfy[h];
+                    }
+#pragma unroll
+                for (int h = 0; h < NXH; ++h)
+                    if (hxl[h] >= 0) {
+                        Ln[hxl[h]] = nhx[h];
+                        if constexpr (ADJ) LFn[hxl[h]] = nfx[h];
+                    }
+            }
+            __syncthreads();
             }
         }
     }
 }
 
 // --------------------------------------------------------------- 2-D step
+// One wavefront per block: 64 columns marching down a chunk of rows with a
+// (2M+1)-row register queue; the current row with its halo is staged in a
+// double-buffered LDS row, and row z+1 is loaded while row z is computed.
 template <int M, bool ADJ>
 __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
                                                const int *__restrict__ prefix, int njobs,
@@ -283,8 +399,8 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
 {
     constexpr int TX = kTileX, LX = TX + 2 * M, Q = 2 * M + 1;
     constexpr Weights<M> W{};
-    __shared__ float sp[LX];
-    __shared__ float sf[ADJ ? LX : 1];
+    __shared__ float sp[2 * LX];
+    __shared__ float sf[ADJ ? 2 * LX : 1];
 
     const int lane = threadIdx.x;
     int b = blockIdx.x;
@@ -304,7 +420,7 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
 
     const int nz = J->nz, nx = J->nx, pitch = J->pitch, nb = J->nb;
     const int64_t fstride = J->fstride;
-    int local = b - prefix[j];
+    const int local = b - prefix[j];
     const int tx = local % J->ntx;
     const int tz = local / J->ntx;
     const int z0 = tz * J->zc, z1 = min(z0 + J->zc, nz);
@@ -314,7 +430,7 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
     const float *fwd = nullptr;
     float *grad = nullptr;
     bool accum = false;
-    if (ADJ) {
+    if constexpr (ADJ) {
         cur = J->adj + (int64_t)((n + 1) & 1) * fstride;
         prv = J->adj + (int64_t)(n & 1) * fstride;
         out = J->adj + (int64_t)(n & 1) * fstride;
@@ -333,80 +449,102 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
     const int x = col - M;
     const bool act = x >= 0 && x < nx;
     const int dxs = sponge_depth(x, nx, nb);
-    float srcv = 0.f;
+    // halo lanes: lane < 2M loads column tx*TX - M + (lane < M ? lane : lane + TX)
+    const int hl = lane < M ? lane : lane + TX;
+    const int hcol = tx * TX - M + hl;
+    const bool hact = lane < 2 * M && hcol >= 0 && hcol < pitch;
     const bool src_here = !ADJ && J->src_x == x && J->src_z >= z0 && J->src_z < z1;
-    if (src_here) srcv = J->src_scale * J->wavelet[n];
+    const float srcv = src_here ? J->src_scale * J->wavelet[n] : 0.f;
+    const int64_t p64 = pitch;
 
     float q[Q];
     float f[ADJ ? Q : 1];
 #pragma unroll
-    for (int s = 0; s < 2 * M; ++s) {
-        const int64_t o = (int64_t)(z0 + s) * pitch + col;   // row z0 - M + s
-        q[s] = act ? cur[o] : 0.f;
-        if constexpr (ADJ) f[s] = act ? fwd[o] : 0.f;
+    for (int s = 0; s < Q; ++s) {   // rows z0 - M .. z0 + M
+        q[s] = act ? cur[(int64_t)(z0 + s) * p64 + col] : 0.f;
+        if constexpr (ADJ) f[s] = act ? fwd[(int64_t)(z0 + s) * p64 + col] : 0.f;
     }
-    for (int z = z0; z < z1; ++z) {
-        const int64_t oz = (int64_t)(z + M) * pitch + col;
-        const int64_t of = oz + (int64_t)M * pitch;
-        q[2 * M] = act ? cur[of] : 0.f;
-        if constexpr (ADJ) f[2 * M] = act ? fwd[of] : 0.f;
-        const float kv = act ? kap[oz] : 0.f;
-        const float pv = act ? prv[oz] : 0.f;
-        sp[M + lane] = q[M];
-        if constexpr (ADJ) sf[M + lane] = f[M];
-        if (lane < 2 * M) {
-            const int lc = lane < M ? lane : lane + TX;
-            const int cm = tx * TX - M + lc;
-            float a = 0.f, bq = 0.f;
-            if (cm >= 0 && cm < pitch) {
-                const int64_t o = (int64_t)(z + M) * pitch + cm;
-                a = cur[o];
-                if constexpr (ADJ) bq = fwd[o];
-            }
-            sp[lc] = a;
-            if constexpr (ADJ) sf[lc] = bq;
+    float kv = act ? kap[(int64_t)(z0 + M) * p64 + col] : 0.f;
+    float pv = act ? prv[(int64_t)(z0 + M) * p64 + col] : 0.f;
+    float gv = 0.f;
+    if constexpr (ADJ) gv = act && accum ? grad[(int64_t)(z0 + M) * p64 + col] : 0.f;
+    {
+        float *L = sp + (z0 & 1) * LX;
+        L[M + lane] = q[M];
+        if (lane < 2 * M) L[hl] = hact ? cur[(int64_t)(z0 + M) * p64 + hcol] : 0.f;
+        if constexpr (ADJ) {
+            float *LF = sf + (z0 & 1) * LX;
+            LF[M + lane] = f[M];
+            if (lane < 2 * M) LF[hl] = hact ? fwd[(int64_t)(z0 + M) * p64 + hcol] : 0.f;
         }
-        __syncthreads();
-        if (act) {
+    }
+    __syncthreads();
+
+    for (int zb = z0; zb < z1; zb += Q) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const int z = zb + k;
+            if (z < z1) {
+            const bool more = z + 1 < z1;
+            float nq = 0.f, nk = 0.f, np = 0.f, nh = 0.f, nfq = 0.f, nfh = 0.f, ng = 0.f;
+            if (more) {
+                const int64_t rf = (int64_t)(z + 1 + 2 * M) * p64, rc = (int64_t)(z + 1 + M) * p64;
+                nq = act ? cur[rf + col] : 0.f;
+                nk = act ? kap[rc + col] : 0.f;
+                np = act ? prv[rc + col] : 0.f;
+                nh = hact ? cur[rc + hcol] : 0.f;
+                if constexpr (ADJ) {
+                    nfq = act ? fwd[rf + col] : 0.f;
+                    nfh = hact ? fwd[rc + hcol] : 0.f;
+                    ng = act && accum ? grad[rc + col] : 0.f;
+                }
+            }
+            const float *L = sp + (z & 1) * LX;
             const int lx = M + lane;
-            const float pc = q[M];
+            const float pc = q[(k + M) % Q];
             float acc = 0.f;
 #pragma unroll
             for (int m = M; m >= 1; --m) {
-                const float d = ((sp[lx + m] - pc) + (sp[lx - m] - pc)) +
-                                ((q[M + m] - pc) + (q[M - m] - pc));
+                const float d = ((L[lx + m] - pc) + (L[lx - m] - pc)) +
+                                ((q[(k + M + m) % Q] - pc) + (q[(k + M - m) % Q] - pc));
                 acc = fmaf(W.c[m], d, acc);
             }
             float val = fmaf(kv, acc, 2.f * pc);
-            if (!ADJ && src_here && z == J->src_z) val += srcv;
+            if (src_here && z == J->src_z) val += srcv;
             const int dz = sponge_depth(z, nz, nb);
-            const int d2 = dxs * dxs + dz * dz;
-            float o;
-            if (d2 == 0) {
-                o = val - pv;
-            } else {
-                const float e = eta_dt * (float)d2;
-                const float a = 1.f / (1.f + e);
-                o = a * val - (1.f - e) * a * pv;
-            }
-            out[oz] = o;
-            if constexpr (ADJ) if (accum) {
-                const float fc = f[M];
-                float lf = 0.f;
+            const int64_t rz = (int64_t)(z + M) * p64 + col;
+            if (act) out[rz] = leapfrog(val, pv, dxs * dxs + dz * dz, eta_dt);
+            if constexpr (ADJ) {
+                if (accum) {
+                    const float *LF = sf + (z & 1) * LX;
+                    const float fc = f[(k + M) % Q];
+                    float lf = 0.f;
 #pragma unroll
-                for (int m = M; m >= 1; --m) {
-                    const float d = ((sf[lx + m] - fc) + (sf[lx - m] - fc)) +
-                                    ((f[M + m] - fc) + (f[M - m] - fc));
-                    lf = fmaf(W.c[m], d, lf);
+                    for (int m = M; m >= 1; --m) {
+                        const float d = ((LF[lx + m] - fc) + (LF[lx - m] - fc)) +
+                                        ((f[(k + M + m) % Q] - fc) + (f[(k + M - m) % Q] - fc));
+                        lf = fmaf(W.c[m], d, lf);
+                    }
+                    if (act) grad[rz] = fmaf(pc, lf, gv);
                 }
-                grad[oz] += pc * lf;
             }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < 2 * M; ++s) {
-            q[s] = q[s + 1];
-            if constexpr (ADJ) f[s] = f[s + 1];
+            if (more) {
+                q[k] = nq;
+                kv = nk;
+                pv = np;
+                float *Ln = sp + ((z + 1) & 1) * LX;
+                Ln[M + lane] = q[(k + M + 1) % Q];
+                if (lane < 2 * M) Ln[hl] = nh;
+                if constexpr (ADJ) {
+                    f[k] = nfq;
+                    gv = ng;
+                    float *LFn = sf + ((z + 1) & 1) * LX;
+                    LFn[M + lane] = f[(k + M + 1) % Q];
+                    if (lane < 2 * M) LFn[hl] = nfh;
+                }
+            }
+            __syncthreads();
+            }
         }
     }
 }
