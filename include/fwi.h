@@ -190,6 +190,58 @@ int fwi_velocity_range(const float *v, int64_t n, float *h_vmin, float *h_vmax, 
 int fwi_revolve_schedule(int32_t nsteps, int32_t slots, int32_t *h_actions, int64_t cap,
                          int64_t *h_count, int64_t *h_forward_steps);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent one-shot jobs.
+ *
+ * A job is one shot (forward, or misfit + gradient) of its own problem (any
+ * grid, 2-D or 3-D, nshots == 1) living in caller-owned device memory `mem`
+ * of fwi_job_bytes bytes, which is the HBM footprint used for admission.
+ * fwi_jobs_advance moves every job of a set forward by one chunk of
+ * `ksteps` time steps of its current phase (forward, checkpoint recompute or
+ * adjoint), putting the steps of all the jobs into shared launches: one
+ * launch per time step per (dimension, order, direction), blocks indexed
+ * over all the jobs' tiles.  Jobs join and leave between chunks.  Each job's
+ * arithmetic is independent of which other jobs share its launches, so its
+ * results are bitwise the same alone and in a mix.
+ * ------------------------------------------------------------------------ */
+typedef struct fwi_job fwi_job;
+
+enum fwi_job_kind { FWI_JOB_FORWARD = 0, FWI_JOB_GRADIENT = 1 };
+
+/* Device bytes one job needs (kind FWI_JOB_*; gradient jobs checkpoint every
+ * `chunk` steps).  Host-only. */
+int fwi_job_bytes(const fwi_problem *prob, int32_t kind, int32_t chunk, uint64_t *h_bytes);
+
+/* Validates and stages a job (synchronises `stream`): as fwi_forward (kind
+ * FORWARD: traces required) or fwi_gradient (kind GRADIENT: obs and dv
+ * required, traces optional), with checkpoints every `chunk` steps.  All
+ * arrays, and `mem`, must stay alive until the job is done and the stream has
+ * passed its last advance.  *h_job receives a host handle (fwi_job_destroy). */
+int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const float *v,
+                   const float *src, const int32_t *src_pos, const int32_t *rec_pos,
+                   const float *obs, float *traces, float *dv, void *mem, uint64_t mem_bytes,
+                   void *stream, fwi_job **h_job);
+
+/* Workspace (device, 256-byte aligned) of one fwi_jobs_advance over njobs jobs. */
+int fwi_jobs_ws_bytes(int32_t njobs, uint64_t *h_bytes);
+
+/* Advances every job by up to ksteps steps of its current phase, in shared
+ * launches on `stream`, and enqueues the per-job operations due around them
+ * (snapshots, final sampling, residual, gradient fold).  Finished jobs are
+ * skipped.  Synchronises `stream` once to upload the launch tables. */
+int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *ws,
+                     uint64_t ws_bytes, void *stream);
+
+/* Host-side state: *h_done = 1 once all of the job's work has been enqueued
+ * (results are valid after the stream has finished it). */
+int fwi_job_query(const fwi_job *job, int32_t *h_done, int64_t *h_ops_left);
+
+/* Misfit of a finished gradient job (synchronises `stream`). */
+int fwi_job_misfit(const fwi_job *job, double *h_misfit, void *stream);
+
+/* Frees the host handle (not `mem`). */
+void fwi_job_destroy(fwi_job *job);
+
 #ifdef __cplusplus
 }
 #endif

@@ -20,7 +20,10 @@ OP_ADVANCE, OP_TAKESHOT, OP_RESTORE, OP_ADJOINT, OP_RESTART = 1, 2, 3, 4, 5
 
 EXPORTS = ["fwi_strerror", "fwi_last_error", "fwi_cfl_limit", "fwi_workspace_bytes",
            "fwi_forward", "fwi_gradient", "fwi_forward_ckpt", "fwi_backward",
-           "fwi_revolve_schedule", "fwi_velocity_range"]
+           "fwi_revolve_schedule", "fwi_velocity_range", "fwi_job_bytes", "fwi_job_create",
+           "fwi_jobs_ws_bytes", "fwi_jobs_advance", "fwi_job_query", "fwi_job_misfit",
+           "fwi_job_destroy"]
+JOB_FORWARD, JOB_GRADIENT = 0, 1
 
 
 class FwiProblem(ctypes.Structure):
@@ -72,8 +75,17 @@ def load():
     lib.fwi_revolve_schedule.argtypes = [i32, i32, P(i32), i64, P(i64), P(i64)]
     lib.fwi_velocity_range.argtypes = [vp, i64, P(ctypes.c_float), P(ctypes.c_float), vp, u64,
                                        vp]
+    lib.fwi_job_bytes.argtypes = [prob, i32, i32, P(u64)]
+    lib.fwi_job_create.argtypes = [prob, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp,
+                                   P(vp)]
+    lib.fwi_jobs_ws_bytes.argtypes = [i32, P(u64)]
+    lib.fwi_jobs_advance.argtypes = [P(vp), i32, i32, vp, u64, vp]
+    lib.fwi_job_query.argtypes = [vp, P(i32), P(i64)]
+    lib.fwi_job_misfit.argtypes = [vp, P(ctypes.c_double), vp]
+    lib.fwi_job_destroy.argtypes = [vp]
+    lib.fwi_job_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("fwi_strerror", "fwi_last_error"):
+        if name not in ("fwi_strerror", "fwi_last_error", "fwi_job_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -156,3 +168,49 @@ def fwi_velocity_range(v, n, ws, ws_bytes, stream):
     _check(load().fwi_velocity_range(v, n, ctypes.byref(lo), ctypes.byref(hi), ws, ws_bytes,
                                      stream), "fwi_velocity_range")
     return lo.value, hi.value
+
+
+def fwi_job_bytes(prob, kind, chunk):
+    out = ctypes.c_uint64()
+    _check(load().fwi_job_bytes(ctypes.byref(prob), kind, chunk, ctypes.byref(out)),
+           "fwi_job_bytes")
+    return out.value
+
+
+def fwi_job_create(prob, kind, chunk, v, src, src_pos, rec_pos, obs, traces, dv, mem,
+                   mem_bytes, stream):
+    h = ctypes.c_void_p()
+    _check(load().fwi_job_create(ctypes.byref(prob), kind, chunk, v, src, src_pos, rec_pos,
+                                 obs, traces, dv, mem, mem_bytes, stream, ctypes.byref(h)),
+           "fwi_job_create")
+    return h
+
+
+def fwi_jobs_ws_bytes(njobs):
+    out = ctypes.c_uint64()
+    _check(load().fwi_jobs_ws_bytes(njobs, ctypes.byref(out)), "fwi_jobs_ws_bytes")
+    return out.value
+
+
+def fwi_jobs_advance(handles, ksteps, ws, ws_bytes, stream):
+    arr = (ctypes.c_void_p * max(len(handles), 1))(*[h.value for h in handles])
+    _check(load().fwi_jobs_advance(arr, len(handles), ksteps, ws, ws_bytes, stream),
+           "fwi_jobs_advance")
+
+
+def fwi_job_query(handle):
+    done = ctypes.c_int32()
+    left = ctypes.c_int64()
+    _check(load().fwi_job_query(handle, ctypes.byref(done), ctypes.byref(left)),
+           "fwi_job_query")
+    return bool(done.value), left.value
+
+
+def fwi_job_misfit(handle, stream):
+    out = ctypes.c_double()
+    _check(load().fwi_job_misfit(handle, ctypes.byref(out), stream), "fwi_job_misfit")
+    return out.value
+
+
+def fwi_job_destroy(handle):
+    load().fwi_job_destroy(handle)

@@ -18,8 +18,7 @@ namespace fwi {
 
 constexpr int kTileX = 64;   // memory columns per tile (one wavefront)
 constexpr int kRowsPerWave = 4;   // 3-D: y rows per thread (register blocking)
-constexpr int kWaves3d = 4;  // 3-D: wavefronts per block
-constexpr int kTileY = kRowsPerWave * kWaves3d;   // 3-D tile height in y
+// 3-D blocks hold 4 or 8 wavefronts: a tile is 64 (x) by kRowsPerWave * waves (y)
 constexpr int kGatherThreads = 256;
 
 struct Job {
@@ -36,9 +35,12 @@ struct Job {
     int32_t ntx, nty, nzc, zc;   // tiles in x and y, z chunks and chunk length
     int32_t ntiles;              // ntx * nty * nzc
     int32_t ngather;             // gather blocks (forward record)
-    // time: forward n = n0 + step, adjoint k = k0 - step
+    // time: forward n = n0 + step, adjoint k = k0 - step; a launch updates a
+    // job only for n in [fwd_lo, fwd_hi) (forward) or k in [adj_lo, adj_hi)
     int32_t n0;
     int32_t k0;
+    int32_t fwd_lo, fwd_hi;
+    int32_t adj_lo, adj_hi;
     int32_t nt;
     int32_t record;        // forward: write traces
     int32_t accumulate;    // adjoint: accumulate the gradient

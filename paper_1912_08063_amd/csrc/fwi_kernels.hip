@@ -110,15 +110,15 @@ __device__ __forceinline__ const float *plane_ptr(const float *f, int zmem, int6
 // the previous level.  While plane z is computed, plane z+1 is already being
 // loaded (the next queue front, kappa', previous level, halos), and written
 // to the other LDS buffer afterwards: one barrier per plane.
-template <int M, bool ADJ>
-__global__ __launch_bounds__(256) void k_step3d(const Job *__restrict__ jobs,
+template <int M, bool ADJ, int NW>
+__global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs,
                                                 const int *__restrict__ prefix, int njobs,
                                                 int step, int ttiles, int remap)
 {
-    constexpr int TX = kTileX, RY = kRowsPerWave, TY = kTileY;
+    constexpr int TX = kTileX, RY = kRowsPerWave, TY = RY * NW, NT = 64 * NW;
     constexpr int LX = TX + 2 * M, LY = TY + 2 * M, Q = 2 * M + 1, LS = LY * LX;
-    constexpr int NYH = (2 * M * TX + 255) / 256;   // y-halo cells per thread
-    constexpr int NXH = (TY * 2 * M + 255) / 256;   // x-halo cells per thread
+    constexpr int NYH = (2 * M * TX + NT - 1) / NT;   // y-halo cells per thread
+    constexpr int NXH = (TY * 2 * M + NT - 1) / NT;   // x-halo cells per thread
     constexpr Weights<M> W{};
     __shared__ float sp[2 * LS];
     __shared__ float sf[ADJ ? 2 * LS : 1];
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void k_step3d(const Job *__restrict__ jobs,
     const int j = find_job(prefix, njobs, b);
     const Job *__restrict__ J = jobs + j;
     const int n = ADJ ? J->k0 - step : J->n0 + step;
-    if (ADJ ? (n < 1 || n > J->nt) : (n < 0 || n >= J->nt)) return;
+    if (ADJ ? (n < J->adj_lo || n >= J->adj_hi) : (n < J->fwd_lo || n >= J->fwd_hi)) return;
 
     const int nz = J->nz, ny = J->ny, nx = J->nx, pitch = J->pitch, nb = J->nb;
     const int64_t plane = J->plane, fstride = J->fstride;
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void k_step3d(const Job *__restrict__ jobs,
     int hyl[NYH], hxl[NXH];
 #pragma unroll
     for (int q = 0; q < NYH; ++q) {   // rows above and below the tile
-        const int h = tid + 256 * q;
+        const int h = tid + NT * q;
         const int r = (h / TX) % (2 * M), c = h % TX;
         const int ly = r < M ? r : r + TY;
         const int yg = ty * TY - M + ly;
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_step3d(const Job *__restrict__ jobs,
     }
 #pragma unroll
     for (int q = 0; q < NXH; ++q) {   // columns left and right of the tile
-        const int h = tid + 256 * q;
+        const int h = tid + NT * q;
         const int r = (h / (2 * M)) % TY, c = h % (2 * M);
         const int lc = c < M ? c : c + TX;
         const int cm = tx * TX - M + lc;
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
     const int j = find_job(prefix, njobs, b);
     const Job *__restrict__ J = jobs + j;
     const int n = ADJ ? J->k0 - step : J->n0 + step;
-    if (ADJ ? (n < 1 || n > J->nt) : (n < 0 || n >= J->nt)) return;
+    if (ADJ ? (n < J->adj_lo || n >= J->adj_hi) : (n < J->fwd_lo || n >= J->fwd_hi)) return;
 
     const int nz = J->nz, nx = J->nx, pitch = J->pitch, nb = J->nb;
     const int64_t fstride = J->fstride;
@@ -618,7 +618,7 @@ __global__ void k_adj_inject(const Job *__restrict__ jobs, const int *__restrict
     const Job *J = jobs + j;
     const int k = J->k0 - step;
     const int r = (blockIdx.x - gprefix[j]) * blockDim.x + threadIdx.x;
-    if (k < 1 || k > J->nt || r >= J->nrec || !J->rec_head[r]) return;
+    if (k < J->adj_lo || k >= J->adj_hi || r >= J->nrec || !J->rec_head[r]) return;
     const float *res = J->res + (int64_t)(k - 1) * J->nrec;
     float s = res[r];
     for (int q = J->rec_next[r]; q >= 0; q = J->rec_next[q]) s += res[q];
@@ -774,19 +774,27 @@ void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st)
     hipLaunchKernelGGL(k_vstats, dim3(vstats_blocks()), dim3(256), 0, st, v, n, partial);
 }
 
+template <int M, int NW>
+static void launch_3d(bool adj, const Job *jobs, const int *prefix, int njobs, int step,
+                      int ttiles, int grid, int remap, hipStream_t st)
+{
+    if (adj)
+        hipLaunchKernelGGL((k_step3d<M, true, NW>), dim3(grid), dim3(64 * NW), 0, st, jobs,
+                           prefix, njobs, step, ttiles, remap);
+    else
+        hipLaunchKernelGGL((k_step3d<M, false, NW>), dim3(grid), dim3(64 * NW), 0, st, jobs,
+                           prefix, njobs, step, ttiles, remap);
+}
+
 template <int M>
-static void launch_step_m(int ndim, bool adj, const Job *jobs, const int *prefix, int njobs,
-                          int step, int ttiles, int gblocks, int remap, hipStream_t st)
+static void launch_step_m(int ndim, int nw, bool adj, const Job *jobs, const int *prefix,
+                          int njobs, int step, int ttiles, int gblocks, int remap, hipStream_t st)
 {
     const int grid = ttiles + (adj ? 0 : gblocks);
     if (grid <= 0) return;
     if (ndim == 3) {
-        if (adj)
-            hipLaunchKernelGGL((k_step3d<M, true>), dim3(grid), dim3(256), 0, st, jobs, prefix,
-                               njobs, step, ttiles, remap);
-        else
-            hipLaunchKernelGGL((k_step3d<M, false>), dim3(grid), dim3(256), 0, st, jobs, prefix,
-                               njobs, step, ttiles, remap);
+        if (nw == 8) launch_3d<M, 8>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, st);
+        else launch_3d<M, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, st);
     } else {
         if (adj)
             hipLaunchKernelGGL((k_step2d<M, true>), dim3(grid), dim3(64), 0, st, jobs, prefix,
@@ -797,14 +805,14 @@ static void launch_step_m(int ndim, bool adj, const Job *jobs, const int *prefix
     }
 }
 
-void launch_step(int ndim, int M, bool adj, const Job *jobs, const int *prefix, int njobs,
-                 int step, int ttiles, int gblocks, int remap, hipStream_t st)
+void launch_step(int ndim, int M, int nw, bool adj, const Job *jobs, const int *prefix,
+                 int njobs, int step, int ttiles, int gblocks, int remap, hipStream_t st)
 {
     switch (M) {
-    case 1: launch_step_m<1>(ndim, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
-    case 2: launch_step_m<2>(ndim, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
-    case 4: launch_step_m<4>(ndim, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
-    case 8: launch_step_m<8>(ndim, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
+    case 1: launch_step_m<1>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
+    case 2: launch_step_m<2>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
+    case 4: launch_step_m<4>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
+    case 8: launch_step_m<8>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
     default: break;
     }
 }

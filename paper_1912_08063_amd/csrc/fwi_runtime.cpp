@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -22,8 +23,8 @@
 #include "revolve.h"
 
 namespace fwi {
-void launch_step(int ndim, int M, bool adj, const Job *jobs, const int *prefix, int njobs,
-                 int step, int ttiles, int gblocks, int remap, hipStream_t st);
+void launch_step(int ndim, int M, int nw, bool adj, const Job *jobs, const int *prefix,
+                 int njobs, int step, int ttiles, int gblocks, int remap, hipStream_t st);
 void launch_prep_kappa(const float *v, float *kappa, int M, int gy, int nz, int ny, int nx,
                        int pitch, int nya, int nb, int nzm, int nym, int nxm, int64_t total,
                        float dt_dx, hipStream_t st);
@@ -259,14 +260,23 @@ void make_layout(const fwi_problem *p, const Geometry &g, const Policy &po, int 
     L->ck_total = c.off;
 }
 
+// wavefronts per 3-D block (4 or 8)
+int waves3d()
+{
+    if (const char *e = getenv("FWI_WAVES")) return atoi(e) == 8 ? 8 : 4;
+    return 4;
+}
+
 void tiles_for(const Geometry &g, int njobs, int *ntx, int *nty, int *nzc, int *zc)
 {
     const int M = g.M;
+    const int ty = kRowsPerWave * waves3d();
     *ntx = (g.nx + M + kTileX - 1) / kTileX;
-    *nty = g.ndim == 3 ? (g.ny + kTileY - 1) / kTileY : 1;
+    *nty = g.ndim == 3 ? (g.ny + ty - 1) / ty : 1;
     const int64_t per = (int64_t)(*ntx) * (*nty) * njobs;
-    // enough blocks to fill 256 CUs several times over
-    int64_t target = g.ndim == 3 ? 2048 : 8192;
+    // about four resident blocks per CU (256 CUs): fewer leaves the memory
+    // system idle, more only adds z-chunk warm-up planes
+    int64_t target = g.ndim == 3 ? 1024 : 8192;
     if (const char *e = getenv("FWI_TARGET_BLOCKS")) target = std::max(1, atoi(e));
     int want = (int)std::max<int64_t>(1, (target + per - 1) / per);
     int z = (g.nz + want - 1) / want;
@@ -277,7 +287,7 @@ void tiles_for(const Geometry &g, int njobs, int *ntx, int *nty, int *nzc, int *
     *nzc = (g.nz + z - 1) / z;
 }
 
-int gather_threads(const Geometry &g) { return g.ndim == 3 ? 256 : 64; }
+int gather_threads(const Geometry &g) { return g.ndim == 3 ? 64 * waves3d() : 64; }
 
 // ------------------------------------------------------------ call context
 struct Ctx {
@@ -293,6 +303,7 @@ struct Ctx {
     int *d_prefix = nullptr;
     int ttiles = 0, gblocks = 0, gthreads = 64;
     int remap = 1;
+    int nw = 4;
     std::vector<int> slot_time;
 
     float *f_at(uint64_t off, bool in_ws) const
@@ -328,6 +339,7 @@ int prepare(Ctx &c, const fwi_problem *p, int mode, const fwi_ckpt *ck, void *ws
     c.ck = static_cast<char *>(ckbuf);
     c.st = static_cast<hipStream_t>(stream);
     if (const char *e = getenv("FWI_XCD_REMAP")) c.remap = atoi(e) != 0;
+    c.nw = waves3d();
     return FWI_OK;
 }
 
@@ -427,6 +439,8 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
         J.ntiles = ntx * nty * nzc;
         J.ngather = ng;
         J.n0 = 0; J.k0 = 0; J.nt = p->nt;
+        J.fwd_lo = 0; J.fwd_hi = p->nt;
+        J.adj_lo = 1; J.adj_hi = p->nt + 1;
         J.record = traces != nullptr;
         J.accumulate = accumulate;
         J.kappa = kappa;
@@ -473,14 +487,14 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
 // ------------------------------------------------------------ time loops
 int fwd_step(Ctx &c, int n, bool record)
 {
-    launch_step(c.g.ndim, c.g.M, false, c.d_jobs, c.d_prefix, c.p->nshots, n, c.ttiles,
+    launch_step(c.g.ndim, c.g.M, c.nw, false, c.d_jobs, c.d_prefix, c.p->nshots, n, c.ttiles,
                 record ? c.gblocks : 0, c.remap, c.st);
     return FWI_OK;
 }
 
 int adj_step(Ctx &c, int k)
 {
-    launch_step(c.g.ndim, c.g.M, true, c.d_jobs, c.d_prefix, c.p->nshots, -k, c.ttiles, 0,
+    launch_step(c.g.ndim, c.g.M, c.nw, true, c.d_jobs, c.d_prefix, c.p->nshots, -k, c.ttiles, 0,
                 c.remap, c.st);
     launch_adj_inject(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
                       c.gthreads, -k, c.st);
@@ -602,6 +616,114 @@ int fold(Ctx &c, const float *v, float *dv)
                 g.nxm, c.f_at(c.L.fold1, true), c.f_at(c.L.fold2, true), v, dv, c.st);
     HIP_TRY(hipGetLastError());
     return FWI_OK;
+}
+
+
+// ------------------------------------------------------------ serving jobs
+// A job is one shot (forward or gradient) with its own device memory and a
+// program of operations.  Step operations (forward or adjoint ranges) are
+// executed a chunk at a time by fwi_jobs_advance, which puts the steps of all
+// active jobs into shared launches; the other operations (snapshots,
+// residual, fold) are per-job launches between chunks.
+enum JobOpType { JOP_FWD, JOP_ADJ, JOP_SNAP, JOP_RESTORE, JOP_ZERO_STATE, JOP_GATHER,
+                 JOP_MISFIT, JOP_ZERO_ADJ, JOP_FOLD };
+
+struct JobOp {
+    int type;
+    int a, b;     // FWD: levels n in [a, b) are advanced; ADJ: k = a down to b
+    int slot;     // SNAP / RESTORE: snapshot slot (time in a)
+    int record;   // FWD: record traces
+};
+
+}  // namespace
+
+struct fwi_job {
+    fwi_problem prob;
+    Ctx c;
+    int kind = 0;
+    int chunk = 0;
+    std::vector<JobOp> ops;
+    size_t head = 0;
+    const float *v = nullptr, *obs = nullptr;
+    float *rec = nullptr, *res = nullptr, *dv = nullptr;
+    double *d_misfit = nullptr;
+};
+
+namespace {
+
+bool is_step(const JobOp &o) { return o.type == JOP_FWD || o.type == JOP_ADJ; }
+
+int run_immediate(fwi_job *J, const JobOp &o)
+{
+    Ctx &c = J->c;
+    const uint64_t fs = (uint64_t)c.g.fstride;
+    switch (o.type) {
+    case JOP_SNAP: return snapshot(c, o.slot, o.a, 0);
+    case JOP_RESTORE: return snapshot(c, o.slot, o.a, 1);
+    case JOP_ZERO_STATE: return snapshot(c, 0, 0, 2);
+    case JOP_GATHER:
+        launch_gather(c.d_jobs, c.d_prefix + 2, 1, c.gblocks, c.gthreads, o.a, c.st);
+        return FWI_OK;
+    case JOP_MISFIT: {
+        const int64_t n = (int64_t)J->prob.nt * J->prob.nrec;
+        if (n > 0)
+            launch_misfit(J->rec, J->obs, J->res, n,
+                          reinterpret_cast<double *>(c.ws + c.L.partial), J->d_misfit, c.st);
+        else
+            launch_fill(reinterpret_cast<float *>(J->d_misfit), 4, 0.f, c.st);
+        return FWI_OK;
+    }
+    case JOP_ZERO_ADJ:
+        zero(c.jobs[0].adj, 2 * fs, c.st);
+        zero(c.jobs[0].grad, fs, c.st);
+        return FWI_OK;
+    case JOP_FOLD: return fold(c, J->v, J->dv);
+    default: return fail(FWI_EINVAL, "internal: bad job op");
+    }
+}
+
+int run_immediates(fwi_job *J)
+{
+    while (J->head < J->ops.size() && !is_step(J->ops[J->head])) {
+        TRY(run_immediate(J, J->ops[J->head]));
+        ++J->head;
+    }
+    return FWI_OK;
+}
+
+void build_program(fwi_job *J)
+{
+    const int nt = J->prob.nt, K = J->chunk;
+    const bool rec = J->prob.nrec > 0;
+    std::vector<JobOp> &ops = J->ops;
+    auto fwd = [&](int a, int b, int record) {
+        for (int s = a; s < b; s += K) ops.push_back(JobOp{JOP_FWD, s, std::min(b, s + K), 0, record});
+    };
+    auto adj = [&](int hi, int lo) {
+        for (int s = hi; s >= lo; s -= K) ops.push_back(JobOp{JOP_ADJ, s, std::max(lo, s - K + 1), 0, 0});
+    };
+    if (J->kind == 0) {   // forward
+        fwd(0, nt, 1);
+        if (rec) ops.push_back(JobOp{JOP_GATHER, nt, 0, 0, 0});
+        return;
+    }
+    const int ctop = J->c.po.ctop;
+    for (int s = 0; s < nt; s += K) {
+        const int e = std::min(nt, s + K);
+        ops.push_back(JobOp{JOP_FWD, s, e, 0, 1});
+        if (e % K == 0 && e <= ctop - K) ops.push_back(JobOp{JOP_SNAP, e, 0, e / K - 1, 0});
+    }
+    if (rec) ops.push_back(JobOp{JOP_GATHER, nt, 0, 0, 0});
+    ops.push_back(JobOp{JOP_MISFIT, 0, 0, 0, 0});
+    ops.push_back(JobOp{JOP_ZERO_ADJ, 0, 0, 0, 0});
+    adj(nt, std::max(ctop, 1));
+    for (int base = ctop - K; base >= 0; base -= K) {
+        if (base == 0) ops.push_back(JobOp{JOP_ZERO_STATE, 0, 0, 0, 0});
+        else ops.push_back(JobOp{JOP_RESTORE, base, 0, base / K - 1, 0});
+        if (K > 1) fwd(base, base + K - 1, 0);
+        adj(base + K - 1, std::max(base, 1));
+    }
+    ops.push_back(JobOp{JOP_FOLD, 0, 0, 0, 0});
 }
 
 }  // namespace
@@ -805,5 +927,204 @@ int fwi_revolve_schedule(int32_t nsteps, int32_t slots, int32_t *h_actions, int6
         return fail(FWI_EINVAL, "internal error");
     }
 }
+
+int fwi_job_bytes(const fwi_problem *prob, int32_t kind, int32_t chunk, uint64_t *h_bytes)
+{
+    if (kind != FWI_JOB_FORWARD && kind != FWI_JOB_GRADIENT) return fail(FWI_EINVAL, "bad job kind");
+    if (chunk < 1) return fail(FWI_EINVAL, "chunk must be >= 1");
+    if (prob && prob->nshots != 1) return fail(FWI_EINVAL, "a job is one shot");
+    fwi_ckpt ck{};
+    ck.kind = FWI_CKPT_EVERY;
+    ck.every = chunk;
+    return fwi_workspace_bytes(prob, kind == FWI_JOB_FORWARD ? FWI_MODE_FORWARD : FWI_MODE_GRADIENT,
+                               &ck, h_bytes);
+}
+
+int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const float *v,
+                   const float *src, const int32_t *src_pos, const int32_t *rec_pos,
+                   const float *obs, float *traces, float *dv, void *mem, uint64_t mem_bytes,
+                   void *stream, fwi_job **h_job)
+{
+    if (!h_job) return fail(FWI_EINVAL, "NULL output");
+    *h_job = nullptr;
+    if (kind != FWI_JOB_FORWARD && kind != FWI_JOB_GRADIENT) return fail(FWI_EINVAL, "bad job kind");
+    if (chunk < 1) return fail(FWI_EINVAL, "chunk must be >= 1");
+    if (!prob || prob->nshots != 1) return fail(FWI_EINVAL, "a job is one shot");
+    try {
+        std::unique_ptr<fwi_job> J(new fwi_job());
+        J->prob = *prob;
+        J->kind = kind;
+        J->chunk = chunk;
+        fwi_ckpt ck{};
+        ck.kind = FWI_CKPT_EVERY;
+        ck.every = chunk;
+        const int mode = kind == FWI_JOB_FORWARD ? FWI_MODE_FORWARD : FWI_MODE_GRADIENT;
+        Ctx &c = J->c;
+        int st = prepare(c, &J->prob, mode, &ck, mem, mem_bytes, nullptr, 0, stream);
+        if (st) return st;
+        const bool rec = prob->nrec > 0;
+        if (!src || (rec && kind == FWI_JOB_FORWARD && !traces)) return fail(FWI_EINVAL, "NULL array");
+        if (kind == FWI_JOB_GRADIENT && (!dv || (rec && !obs))) return fail(FWI_EINVAL, "NULL array");
+        J->v = v;
+        J->obs = obs;
+        J->dv = dv;
+        if (kind == FWI_JOB_GRADIENT) {
+            J->res = c.f_at(c.L.res, true);
+            J->d_misfit = reinterpret_cast<double *>(c.ws + c.L.misfit);
+            J->rec = traces ? traces : J->res;
+        } else {
+            J->rec = traces;
+        }
+        st = stage(c, v, src, src_pos, rec_pos, rec ? J->rec : nullptr, J->res,
+                   kind == FWI_JOB_GRADIENT);
+        if (st) return st;
+        zero(c.jobs[0].ring, (uint64_t)c.g.fstride * c.po.R, c.st);
+        HIP_TRY(hipGetLastError());
+        build_program(J.get());
+        *h_job = J.release();
+        return FWI_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FWI_EINVAL, "host allocation failed");
+    } catch (...) {
+        return fail(FWI_EINVAL, "internal error");
+    }
+}
+
+int fwi_jobs_ws_bytes(int32_t njobs, uint64_t *h_bytes)
+{
+    if (njobs < 0 || !h_bytes) return fail(FWI_EINVAL, "bad argument");
+    // at most 16 launch groups (2-D/3-D x forward/adjoint x 4 orders), each a
+    // job table and two prefix arrays
+    *h_bytes = 16 * (align_up(sizeof(Job) * (uint64_t)njobs, kAlign) +
+                    align_up(sizeof(int) * 2ull * (njobs + 1), kAlign)) + kAlign;
+    return FWI_OK;
+}
+
+int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *ws,
+                     uint64_t ws_bytes, void *stream)
+{
+    if (njobs < 0 || (njobs > 0 && !jobs) || ksteps < 1) return fail(FWI_EINVAL, "bad argument");
+    uint64_t need = 0;
+    fwi_jobs_ws_bytes(njobs, &need);
+    if (!ws || ws_bytes < need) return fail(FWI_ENOMEM, "advance workspace too small");
+    if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0)
+        return fail(FWI_EINVAL, "workspace must be 256-byte aligned");
+    try {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        for (int i = 0; i < njobs; ++i) {
+            if (!jobs[i]) return fail(FWI_EINVAL, "NULL job");
+            jobs[i]->c.st = st;
+        }
+        // 1. operations due before this chunk's steps
+        for (int i = 0; i < njobs; ++i) TRY(run_immediates(jobs[i]));
+        // 2. gather this chunk's step ranges into launch groups
+        struct Group {
+            int ndim = 0, M = 0, adj = 0, nw = 4, steps = 0;
+            std::vector<Job> table;
+            std::vector<int> tp{0}, gp{0};
+            Job *d_jobs = nullptr;
+            int *d_prefix = nullptr;
+            int gthreads = 64;
+        };
+        std::vector<Group> groups;
+        auto group_of = [&](int ndim, int M, int adj, int nw) -> Group & {
+            for (Group &g : groups)
+                if (g.ndim == ndim && g.M == M && g.adj == adj && g.nw == nw) return g;
+            groups.push_back(Group{});
+            Group &g = groups.back();
+            g.ndim = ndim; g.M = M; g.adj = adj; g.nw = nw;
+            return g;
+        };
+        for (int i = 0; i < njobs; ++i) {
+            fwi_job *J = jobs[i];
+            if (J->head >= J->ops.size()) continue;
+            JobOp &o = J->ops[J->head];
+            Job t = J->c.jobs[0];
+            int steps;
+            if (o.type == JOP_FWD) {
+                steps = std::min(ksteps, o.b - o.a);
+                t.n0 = o.a;
+                t.fwd_lo = o.a;
+                t.fwd_hi = o.a + steps;
+                t.record = o.record && J->rec;
+                o.a += steps;
+            } else {
+                steps = std::min(ksteps, o.a - o.b + 1);
+                t.k0 = o.a;
+                t.adj_hi = o.a + 1;
+                t.adj_lo = o.a - steps + 1;
+                o.a -= steps;
+            }
+            const bool finished = o.type == JOP_FWD ? o.a >= o.b : o.a < o.b;
+            if (finished) ++J->head;
+            Group &g = group_of(J->c.g.ndim, J->c.g.M, o.type == JOP_ADJ, J->c.nw);
+            g.steps = std::max(g.steps, steps);
+            g.gthreads = J->c.gthreads;
+            g.table.push_back(t);
+            g.tp.push_back(g.tp.back() + t.ntiles);
+            g.gp.push_back(g.gp.back() + ((o.type == JOP_FWD && t.record) || o.type == JOP_ADJ
+                                              ? t.ngather : 0));
+        }
+        // 3. upload the tables and launch every step of the chunk for all groups
+        char *w = static_cast<char *>(ws);
+        uint64_t off = 0;
+        for (Group &g : groups) {
+            const int n = (int)g.table.size();
+            g.d_jobs = reinterpret_cast<Job *>(w + off);
+            off += align_up(sizeof(Job) * (uint64_t)n, kAlign);
+            g.d_prefix = reinterpret_cast<int *>(w + off);
+            off += align_up(sizeof(int) * 2ull * (n + 1), kAlign);
+            std::vector<int> pre(g.tp);
+            pre.insert(pre.end(), g.gp.begin(), g.gp.end());
+            HIP_TRY(hipMemcpyAsync(g.d_jobs, g.table.data(), sizeof(Job) * n,
+                                   hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(g.d_prefix, pre.data(), sizeof(int) * pre.size(),
+                                   hipMemcpyHostToDevice, st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));   // host tables die with this frame
+        for (int j = 0; j < ksteps; ++j) {
+            for (Group &g : groups) {
+                if (j >= g.steps) continue;
+                const int n = (int)g.table.size();
+                const int ttiles = g.tp.back(), gblocks = g.gp.back();
+                launch_step(g.ndim, g.M, g.nw, g.adj != 0, g.d_jobs, g.d_prefix, n, j, ttiles,
+                            g.adj ? 0 : gblocks, 1, st);
+                if (g.adj)
+                    launch_adj_inject(g.d_jobs, g.d_prefix + n + 1, n, gblocks, g.gthreads, j, st);
+            }
+        }
+        HIP_TRY(hipGetLastError());
+        // 4. operations due right after this chunk (final gather, residual, fold)
+        for (int i = 0; i < njobs; ++i) TRY(run_immediates(jobs[i]));
+        HIP_TRY(hipGetLastError());
+        return FWI_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FWI_EINVAL, "host allocation failed");
+    } catch (...) {
+        return fail(FWI_EINVAL, "internal error");
+    }
+}
+
+int fwi_job_query(const fwi_job *job, int32_t *h_done, int64_t *h_ops_left)
+{
+    if (!job) return fail(FWI_EINVAL, "NULL job");
+    const int64_t left = (int64_t)job->ops.size() - (int64_t)job->head;
+    if (h_done) *h_done = left == 0;
+    if (h_ops_left) *h_ops_left = left;
+    return FWI_OK;
+}
+
+int fwi_job_misfit(const fwi_job *job, double *h_misfit, void *stream)
+{
+    if (!job || !h_misfit) return fail(FWI_EINVAL, "bad argument");
+    if (job->kind != FWI_JOB_GRADIENT) return fail(FWI_EINVAL, "not a gradient job");
+    if (job->head < job->ops.size()) return fail(FWI_EINVAL, "job not finished");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(h_misfit, job->d_misfit, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return FWI_OK;
+}
+
+void fwi_job_destroy(fwi_job *job) { delete job; }
 
 }  // extern "C"

@@ -1,0 +1,318 @@
+"""Continuous-batching server for shot simulations and FWI gradients.
+
+Requests -- forward modelling, or misfit and gradient, of one shot on its own
+2-D or 3-D grid -- arrive as a Poisson stream.  A request is admitted when a
+slot is free and its HBM footprint (the job memory of fwi_job_bytes plus its
+inputs and outputs) fits the free budget; its velocity model and wavefield
+state then stay resident on the device until it finishes.  Every chunk of K
+time steps, all admitted jobs advance together through fwi_jobs_advance,
+whose launches each cover the tiles of every job; requests that arrived in
+the meantime join at the next chunk boundary and finished ones leave.
+
+The plain baseline is the same loop with one slot: one request at a time,
+each with launches of its own.
+
+    python -m paper_1912_08063_amd.serve --requests 200 --rate 0.8
+"""
+from __future__ import annotations
+
+import argparse
+import dataclasses
+import json
+import sys
+import time
+from typing import List, Optional
+
+import numpy as np
+
+from . import workloads as wl
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    kind: str                      # "forward" or "gradient"
+    arrival: float                 # seconds after the stream starts
+    problem: wl.Problem            # one shot
+    obs: Optional[np.ndarray] = None   # gradient: observed traces [1][nt][R]
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    kind: str
+    arrival: float
+    admitted: float
+    done: float
+    traces: Optional[np.ndarray] = None
+    dv: Optional[np.ndarray] = None
+    misfit: Optional[float] = None
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+def _round16(x):
+    return max(16, int(round(x / 16.0)) * 16)
+
+
+def make_request_problem(rid, seed=4, scale=1.0, force=None):
+    """One request of the mixed stream: 2-D N^2 with N ~ U[256, 2048] or 3-D N^3
+    with N ~ U[128, 384] (50/50, rounded to 16), 1000-4000 steps, layered
+    model (8-12 layers, 1500-4500 m/s, 5 % noise), 10 Hz Ricker at the surface,
+    dt from CFL 0.4, 20 (2-D) / 24 (3-D) sponge cells.  `scale` shrinks the
+    grid edge and the step count (tests)."""
+    rng = np.random.default_rng(seed + rid)
+    kind = "gradient" if rng.random() < 0.3 else "forward"
+    dim = 2 if rng.random() < 0.5 else 3
+    if force:
+        kind = force.get("kind", kind)
+        dim = force.get("dim", dim)
+    if dim == 2:
+        n = _round16(rng.uniform(256, 2048) * scale)
+        shape = (n, n)
+        nb = 20
+    else:
+        n = _round16(rng.uniform(128, 384) * scale)
+        shape = (n, n, n)
+        nb = 24
+    nt = max(8, int(rng.integers(1000, 4001) * scale))
+    v = wl.layered(shape, rng)
+    dx = 10.0
+    dt = wl.dt_from_cfl(float(v.max()), dx, 0.4)
+    src = [[4] + [s // 2 for s in shape[1:]]]
+    rec = wl.surface_receivers(shape, 4, stride=1 if dim == 2 else 4)
+    P = wl._pack("req%d-%s-%dd-%d-nt%d" % (rid, kind, dim, n, nt), v, dx, dt, nt, 8, nb, 10.0,
+                 src, rec)
+    return kind, P
+
+
+def make_stream(n, rate, seed=4, scale=1.0, force=None) -> List[Request]:
+    """n requests with exponential inter-arrival times of mean 1/rate seconds."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n)) if rate > 0 else np.zeros(n)
+    out = []
+    for i in range(n):
+        kind, P = make_request_problem(i, seed, scale, force)
+        out.append(Request(i, kind, float(t[i]), P))
+    return out
+
+
+def attach_observed(requests, device="cuda", perturb=1.02):
+    """Observed data of gradient requests: the library's forward on perturb * v
+    (computed before the stream starts, not timed)."""
+    import torch
+    from . import api
+    for r in requests:
+        if r.kind != "gradient" or r.obs is not None:
+            continue
+        P = r.problem
+        t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=device).to(d)
+        cfg = api.Config(dt=P.dt, dx=P.dx, order=P.order, nsponge=P.nb, eta_max=P.eta_max)
+        tr = api.forward(t(P.v * perturb, torch.float32), t(P.wavelet, torch.float32),
+                         t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32), cfg)
+        r.obs = tr.cpu().numpy()
+    return requests
+
+
+class _Active:
+    pass
+
+
+class Server:
+    """Admission by HBM footprint, resident job state, continuous batching."""
+
+    def __init__(self, device="cuda", hbm_budget=None, max_active=64, chunk=50,
+                 keep_outputs=False):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        if hbm_budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            hbm_budget = int(0.8 * free)
+        self.budget = int(hbm_budget)
+        self.max_active = int(max_active)
+        self.chunk = int(chunk)
+        self.keep = keep_outputs
+        self.ws = None
+
+    # ---------------------------------------------------------------- sizes
+    def _problem(self, P):
+        from . import _lib
+        p = _lib.FwiProblem()
+        p.ndim = P.v.ndim
+        for i, n in enumerate(P.v.shape):
+            p.shape[i] = int(n)
+        p.dx, p.dt, p.nt = P.dx, P.dt, P.nt
+        p.order, p.nsponge, p.eta_max = P.order, P.nb, P.eta_max
+        p.nshots, p.nrec = 1, P.nrec
+        return p
+
+    def footprint(self, req: Request) -> int:
+        from . import _lib
+        P = req.problem
+        kind = _lib.JOB_GRADIENT if req.kind == "gradient" else _lib.JOB_FORWARD
+        job = _lib.fwi_job_bytes(self._problem(P), kind, self.chunk)
+        io = 4 * (P.v.size + P.nt + P.nt * P.nrec * (2 if req.kind == "gradient" else 1))
+        io += 4 * P.v.size if req.kind == "gradient" else 0
+        return job + io + 4 * P.src_pos.size + 4 * P.rec_pos.size
+
+    # -------------------------------------------------------------- admission
+    def _admit(self, req: Request, now):
+        from . import _lib
+        torch = self.torch
+        P = req.problem
+        dev = self.device
+        t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
+        a = _Active()
+        a.req = req
+        a.admitted = now
+        a.v = t(P.v, torch.float32)
+        a.w = t(P.wavelet, torch.float32)
+        a.s = t(P.src_pos, torch.int32)
+        a.r = t(P.rec_pos, torch.int32)
+        grad = req.kind == "gradient"
+        a.obs = t(req.obs, torch.float32) if grad else None
+        a.traces = torch.empty((1, P.nt, P.nrec), dtype=torch.float32, device=dev)
+        a.dv = torch.empty_like(a.v) if grad else None
+        kind = _lib.JOB_GRADIENT if grad else _lib.JOB_FORWARD
+        prob = self._problem(P)
+        nbytes = _lib.fwi_job_bytes(prob, kind, self.chunk)
+        a.mem = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        a.footprint = self.footprint(req)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        a.handle = _lib.fwi_job_create(
+            prob, kind, self.chunk, a.v.data_ptr(), a.w.data_ptr(), a.s.data_ptr(),
+            a.r.data_ptr() if P.nrec else None, a.obs.data_ptr() if grad and P.nrec else None,
+            a.traces.data_ptr() if P.nrec else None, a.dv.data_ptr() if grad else None,
+            a.mem.data_ptr(), a.mem.numel(), stream)
+        return a
+
+    def _finish(self, a, now):
+        from . import _lib
+        torch = self.torch
+        res = Result(a.req.rid, a.req.kind, a.req.arrival, a.admitted, now)
+        if a.req.kind == "gradient":
+            res.misfit = _lib.fwi_job_misfit(a.handle, torch.cuda.current_stream(
+                self.device).cuda_stream)
+        if self.keep:
+            res.traces = a.traces.cpu().numpy()
+            if a.dv is not None:
+                res.dv = a.dv.cpu().numpy()
+        _lib.fwi_job_destroy(a.handle)
+        return res
+
+    # ------------------------------------------------------------------- loop
+    def run(self, requests: List[Request], realtime=True, log=None):
+        """Serves the stream; returns (results, report dict)."""
+        from . import _lib
+        torch = self.torch
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        for r in pending:
+            if r.kind == "gradient" and r.obs is None:
+                raise ValueError("gradient request %d has no observed data" % r.rid)
+        active, results = [], []
+        used = 0
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        ws_bytes = _lib.fwi_jobs_ws_bytes(self.max_active)
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        t0 = time.perf_counter()
+        clock = (lambda: time.perf_counter() - t0) if realtime else None
+        virtual = 0.0
+        chunks = 0
+        while pending or active:
+            now = clock() if realtime else virtual
+            # admit arrived requests while slots and memory allow
+            while pending and len(active) < self.max_active:
+                r = pending[0]
+                if realtime and r.arrival > now:
+                    break
+                need = self.footprint(r)
+                if used + need > self.budget and active:
+                    break
+                if need > self.budget:
+                    raise MemoryError("request %d needs %d bytes > budget %d" %
+                                      (r.rid, need, self.budget))
+                pending.pop(0)
+                a = self._admit(r, now)
+                used += a.footprint
+                active.append(a)
+            if not active:
+                if realtime and pending:
+                    time.sleep(max(0.0, min(0.01, pending[0].arrival - clock())))
+                elif pending:
+                    virtual = max(virtual, pending[0].arrival)
+                continue
+            _lib.fwi_jobs_advance([a.handle for a in active], self.chunk, self.ws.data_ptr(),
+                                  ws_bytes, stream)
+            torch.cuda.synchronize(self.device)
+            chunks += 1
+            now = clock() if realtime else virtual
+            still = []
+            for a in active:
+                done, _ = _lib.fwi_job_query(a.handle)
+                if done:
+                    results.append(self._finish(a, now))
+                    used -= a.footprint
+                    if log:
+                        log("request %d (%s) done: latency %.3f s" % (a.req.rid, a.req.kind,
+                                                                      results[-1].latency))
+                else:
+                    still.append(a)
+            active = still
+        makespan = (clock() if realtime else virtual)
+        lat = np.array([r.latency for r in results])
+        report = {
+            "requests": len(results), "chunks": chunks, "chunk_steps": self.chunk,
+            "max_active": self.max_active, "makespan_s": makespan,
+            "shots_per_s": len(results) / makespan if makespan > 0 else None,
+            "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+            "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+            "mean_latency_s": float(lat.mean()) if len(lat) else None,
+        }
+        return sorted(results, key=lambda r: r.rid), report
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--rate", type=float, default=None,
+                    help="arrivals per second (default: 0.8 x the measured saturated rate)")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--chunk", type=int, default=50)
+    ap.add_argument("--max-active", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--skip-plain", action="store_true")
+    args = ap.parse_args(argv)
+    log = lambda m: print("[serve] " + m, file=sys.stderr, flush=True)
+    reqs = make_stream(args.requests, 1.0, args.seed, args.scale)
+    log("observed data for %d gradient requests" % sum(r.kind == "gradient" for r in reqs))
+    attach_observed(reqs)
+    rate = args.rate
+    out = {}
+    if rate is None:
+        # saturated throughput: everything arrives at t = 0
+        for r in reqs:
+            r.arrival = 0.0
+        _, sat = Server(max_active=args.max_active, chunk=args.chunk).run(reqs, realtime=True)
+        out["saturated"] = sat
+        rate = 0.8 * sat["shots_per_s"]
+        log("saturated: %.2f shots/s" % sat["shots_per_s"])
+    arr = np.cumsum(np.random.default_rng(args.seed).exponential(1.0 / rate, len(reqs)))
+    for r, t in zip(reqs, arr):
+        r.arrival = float(t)
+    _, rep = Server(max_active=args.max_active, chunk=args.chunk).run(reqs, realtime=True)
+    out["batched"] = dict(rep, rate=rate)
+    log("batched: p50 %.3f s p99 %.3f s" % (rep["p50_latency_s"], rep["p99_latency_s"]))
+    if not args.skip_plain:
+        _, rep1 = Server(max_active=1, chunk=args.chunk).run(reqs, realtime=True)
+        out["plain"] = dict(rep1, rate=rate)
+        log("plain: p50 %.3f s p99 %.3f s" % (rep1["p50_latency_s"], rep1["p99_latency_s"]))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

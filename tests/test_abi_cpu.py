@@ -38,7 +38,7 @@ def _prob(**kw):
 
 def test_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "fwi.h")).read()
-    declared = set(re.findall(r"^(?:int|const char \*)\s*(fwi_\w+)\(", header, re.M))
+    declared = set(re.findall(r"^(?:int|void|const char \*)\s*(fwi_\w+)\(", header, re.M))
     assert declared == set(_lib.EXPORTS)
     lib = _lib.load()
     for name in declared:

@@ -1,0 +1,96 @@
+"""Serving: jobs of different grids batched into shared launches.
+
+Each job's results must be bitwise those of the stand-alone entry points
+(fwi_forward / fwi_gradient with the same checkpoint interval) and the same
+alone and in a mix; a job served in a mix also matches the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import f32, oracle_forward, oracle_gradient, rel_l2
+from paper_1912_08063_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _stream(n, scale, seed=21, force=None):
+    from paper_1912_08063_amd import serve
+    reqs = serve.make_stream(n, 0.0, seed=seed, scale=scale, force=force)
+    for r in reqs:
+        r.problem = f32(r.problem)
+    serve.attach_observed(reqs)
+    return reqs
+
+
+def _standalone(req, chunk):
+    import torch
+    from gpu_common import cfg, dev, inputs
+    from paper_1912_08063_amd import api
+    P = req.problem
+    v, w, s, r = inputs(P)
+    if req.kind == "forward":
+        tr = api.forward(v, w, s, r, cfg(P))
+        torch.cuda.synchronize()
+        return tr.cpu().numpy(), None, None
+    mis, dv, tr = api.gradient(v, dev(req.obs, torch.float32), w, s, r,
+                               cfg(P, "every:%d" % chunk), return_traces=True)
+    torch.cuda.synchronize()
+    return tr.cpu().numpy(), dv.cpu().numpy(), mis
+
+
+def test_mixed_jobs_bitwise_equal_standalone_calls():
+    from paper_1912_08063_amd import serve
+    reqs = _stream(10, 0.08)
+    kinds = {(r.kind, r.problem.ndim) for r in reqs}
+    assert len(kinds) >= 3, kinds
+    chunk = 16
+    results, rep = serve.Server(max_active=10, chunk=chunk, keep_outputs=True).run(
+        reqs, realtime=False)
+    assert rep["requests"] == 10
+    for req, res in zip(reqs, results):
+        tr, dv, mis = _standalone(req, chunk)
+        assert np.array_equal(res.traces, tr), req.problem.name
+        if req.kind == "gradient":
+            assert np.array_equal(res.dv, dv), req.problem.name
+            assert res.misfit == mis
+
+
+def test_alone_and_in_a_mix_are_identical():
+    from paper_1912_08063_amd import serve
+    reqs = _stream(8, 0.06, seed=33)
+    alone, _ = serve.Server(max_active=1, chunk=20, keep_outputs=True).run(reqs, realtime=False)
+    mixed, rep = serve.Server(max_active=8, chunk=20, keep_outputs=True).run(reqs,
+                                                                             realtime=False)
+    assert rep["requests"] == 8
+    for a, b in zip(alone, mixed):
+        assert np.array_equal(a.traces, b.traces)
+        if a.kind == "gradient":
+            assert np.array_equal(a.dv, b.dv) and a.misfit == b.misfit
+
+
+def test_served_job_matches_oracle():
+    from paper_1912_08063_amd import serve
+    reqs = _stream(4, 0.05, seed=5, force={"dim": 2})
+    reqs[0].kind = "gradient"
+    serve.attach_observed(reqs)
+    results, _ = serve.Server(max_active=4, chunk=12, keep_outputs=True).run(reqs,
+                                                                            realtime=False)
+    for req, res in zip(reqs, results):
+        P = req.problem
+        if req.kind == "forward":
+            assert rel_l2(res.traces.astype(np.float64), oracle_forward(P)) <= 1e-4
+        else:
+            obs = req.obs.astype(np.float64)
+            mis_o, dv_o = oracle_gradient(P, P.v, obs)
+            assert rel_l2(res.dv.astype(np.float64), dv_o) <= 1e-3
+            assert abs(res.misfit - mis_o) <= 1e-3 * mis_o
+
+
+def test_admission_respects_budget():
+    from paper_1912_08063_amd import serve
+    reqs = _stream(6, 0.05, seed=8)
+    srv = serve.Server(max_active=6, chunk=10)
+    biggest = max(srv.footprint(r) for r in reqs)
+    srv.budget = biggest + 1   # at most one large job at a time
+    results, rep = srv.run(reqs, realtime=False)
+    assert rep["requests"] == 6
