@@ -31,6 +31,21 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def recorded_traffic():
+    """HBM bytes per step launch from the rocprofv3 counter runs recorded in
+    profiles/, or None if the kernel or runtime source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_step3d_fwd_c2.json")
+    try:
+        rec = json.load(open(path))
+        for src, digest in rec["sources_sha1"].items():
+            if hashlib.sha1(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != digest:
+                return None
+        return rec["traffic_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def cpu_baseline(P, nt_sample):
     """The oracle as it stands, on the same model for nt_sample steps."""
     import oracle
@@ -45,6 +60,73 @@ def cpu_baseline(P, nt_sample):
                       "(%.1f s, set-up included)" % (nt_sample, P.nt, secs)}
 
 
+def gradient_section(dev, nt, shots, every):
+    """C3: 2-D FWI gradient, 32 shots.  Batched: one fwi_gradient call for all
+    shots (each launch covers every shot's tiles).  Plain: one call per shot."""
+    import numpy as np
+    import torch
+
+    from paper_1912_08063_amd import api, workloads as wl
+    P = wl.c3(nt=nt, nshots=shots)
+    t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
+    w, s, r = t(P.wavelet, torch.float32), t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
+    cfg = api.Config(dt=P.dt, dx=P.dx, order=P.order, nsponge=P.nb, eta_max=P.eta_max,
+                     ckpt="every:%d" % every)
+    obs = api.forward(t(P.v, torch.float32), w, s, r, cfg)          # untimed
+    v0 = t(P.v_start, torch.float32)
+    ws = api.Workspace()
+    api.gradient(v0, obs, w, s, r, cfg, workspace=ws)               # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mis, dv = api.gradient(v0, obs, w, s, r, cfg, workspace=ws)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    log("gradient batched: %d shots in %.3f s" % (shots, tb))
+    ws1 = api.Workspace()
+    api.gradient(v0, obs[:1], w[:1], s[:1], r[:1], cfg, workspace=ws1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(shots):
+        api.gradient(v0, obs[i:i + 1], w[i:i + 1], s[i:i + 1], r[i:i + 1], cfg, workspace=ws1)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    log("gradient plain: %d shots in %.3f s" % (shots, tp))
+    return {"workload": "2-D FWI gradient, 1024x320 model + 20-cell sponge, %d shots, %d steps, "
+                        "1024 receivers, every-%d checkpoints" % (shots, nt, every),
+            "batched_shots_per_s": round(shots / tb, 3), "plain_shots_per_s": round(shots / tp, 3),
+            "speedup": round(tp / tb, 3), "misfit": mis}
+
+
+def serve_section(nreq, scale, chunk):
+    """C4 (reduced grid/step scale): Poisson stream of mixed 2-D/3-D forward and
+    gradient requests at 0.8x the saturated rate; continuous batching vs one
+    request at a time."""
+    import numpy as np
+
+    from paper_1912_08063_amd import serve
+    reqs = serve.make_stream(nreq, 1.0, seed=4, scale=scale)
+    serve.attach_observed(reqs)
+    for r in reqs:
+        r.arrival = 0.0
+    _, sat = serve.Server(max_active=64, chunk=chunk).run(reqs, realtime=True)
+    rate = 0.8 * sat["shots_per_s"]
+    arr = np.cumsum(np.random.default_rng(4).exponential(1.0 / rate, nreq))
+    for r, a in zip(reqs, arr):
+        r.arrival = float(a)
+    _, b = serve.Server(max_active=64, chunk=chunk).run(reqs, realtime=True)
+    log("serving batched: p50 %.3f p99 %.3f s" % (b["p50_latency_s"], b["p99_latency_s"]))
+    _, p = serve.Server(max_active=1, chunk=chunk).run(reqs, realtime=True)
+    log("serving plain: p50 %.3f p99 %.3f s" % (p["p50_latency_s"], p["p99_latency_s"]))
+    keep = ("shots_per_s", "p50_latency_s", "p99_latency_s", "makespan_s")
+    return {"workload": "Poisson stream of %d requests (70%% forward / 30%% gradient; 2-D and "
+                        "3-D layered models), grid edges and step counts x%.2f of the full "
+                        "stream, arrival rate 0.8x saturated" % (nreq, scale),
+            "rate_per_s": round(rate, 3),
+            "saturated_shots_per_s": round(sat["shots_per_s"], 3),
+            "batched": {k: round(b[k], 4) for k in keep},
+            "plain": {k: round(p[k], 4) for k in keep}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +135,12 @@ def main():
     ap.add_argument("--nt", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sections", default="forward,gradient,serve",
+                    help="comma list of: forward (headline), gradient (C3), serve (C4)")
+    ap.add_argument("--grad-nt", type=int, default=3000)
+    ap.add_argument("--grad-shots", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -145,11 +233,16 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": "k_step3d<4,false> (stencil step, one launch per time step)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(),
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_us": round(avg_launch_s * 1e6, 2),
         },
     }
+    sections = set(args.sections.split(","))
+    if "gradient" in sections:
+        out["gradient"] = gradient_section(dev, args.grad_nt, args.grad_shots, 50)
+    if "serve" in sections:
+        out["serving"] = serve_section(args.serve_requests, args.serve_scale, 50)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %d steps)" % args.cpu_steps)
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps)

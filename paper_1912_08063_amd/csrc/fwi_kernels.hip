@@ -119,6 +119,10 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     constexpr int LX = TX + 2 * M, LY = TY + 2 * M, Q = 2 * M + 1, LS = LY * LX;
     constexpr int NYH = (2 * M * TX + NT - 1) / NT;   // y-halo cells per thread
     constexpr int NXH = (TY * 2 * M + NT - 1) / NT;   // x-halo cells per thread
+    // forward: halos travel with the queue front (loaded at plane z+M, the
+    // same iteration in which the neighbouring tiles load those rows as their
+    // own front, so the second read is an L2 hit) and wait in a register ring
+    constexpr bool HQ = !ADJ;
     constexpr Weights<M> W{};
     __shared__ float sp[2 * LS];
     __shared__ float sf[ADJ ? 2 * LS : 1];
@@ -223,6 +227,18 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     // ---- prologue: queue slots 0..2M hold planes z0-M .. z0+M; plane z0 in LDS
     float q[RY][Q];
     float f[ADJ ? RY : 1][ADJ ? Q : 1];
+    float hy[HQ ? NYH : 1][HQ ? Q : 1], hx[HQ ? NXH : 1][HQ ? Q : 1];
+    if constexpr (HQ) {
+        // halo ring: slot s holds the halos of plane z0 - M + s (s = M+1 .. 2M now)
+#pragma unroll
+        for (int s = M + 1; s < Q; ++s) {
+            const float *ph = plane_ptr(cur, z0 + s, plane);
+#pragma unroll
+            for (int h = 0; h < NYH; ++h) hy[h][s] = hyv[h] ? ph[hyo[h]] : 0.f;
+#pragma unroll
+            for (int h = 0; h < NXH; ++h) hx[h][s] = hxv[h] ? ph[hxo[h]] : 0.f;
+        }
+    }
 #pragma unroll
     for (int s = 0; s < Q; ++s) {
         const float *pc = plane_ptr(cur, z0 + s, plane);   // grid plane z0 - M + s
@@ -287,10 +303,11 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                     nk[i] = act[i] ? pk[roff[i]] : 0.f;
                     np[i] = act[i] ? pp[roff[i]] : 0.f;
                 }
+                const float *phq = HQ ? plane_ptr(cur, z + 1 + 2 * M, plane) : ph;
 #pragma unroll
-                for (int h = 0; h < NYH; ++h) nhy[h] = hyv[h] ? ph[hyo[h]] : 0.f;
+                for (int h = 0; h < NYH; ++h) nhy[h] = hyv[h] ? phq[hyo[h]] : 0.f;
 #pragma unroll
-                for (int h = 0; h < NXH; ++h) nhx[h] = hxv[h] ? ph[hxo[h]] : 0.f;
+                for (int h = 0; h < NXH; ++h) nhx[h] = hxv[h] ? phq[hxo[h]] : 0.f;
                 if constexpr (ADJ) {
                     const float *fq = plane_ptr(fwd, z + 1 + 2 * M, plane);
                     const float *fh = plane_ptr(fwd, z + 1 + M, plane);
@@ -372,13 +389,23 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
 #pragma unroll
                 for (int h = 0; h < NYH; ++h)
                     if (hyl[h] >= 0) {
-                        Ln[hyl[h]] = nhy[h];
+                        if constexpr (HQ) {
+                            Ln[hyl[h]] = hy[h][(k + M + 1) % Q];
+                            hy[h][k] = nhy[h];
+                        } else {
+                            Ln[hyl[h]] = nhy[h];
+                        }
                         if constexpr (ADJ) LFn[hyl[h]] = nfy[h];
                     }
 #pragma unroll
                 for (int h = 0; h < NXH; ++h)
                     if (hxl[h] >= 0) {
-                        Ln[hxl[h]] = nhx[h];
+                        if constexpr (HQ) {
+                            Ln[hxl[h]] = hx[h][(k + M + 1) % Q];
+                            hx[h][k] = nhx[h];
+                        } else {
+                            Ln[hxl[h]] = nhx[h];
+                        }
                         if constexpr (ADJ) LFn[hxl[h]] = nfx[h];
                     }
             }
@@ -802,6 +829,37 @@ static void launch_step_m(int ndim, int nw, bool adj, const Job *jobs, const int
         else
             hipLaunchKernelGGL((k_step2d<M, false>), dim3(grid), dim3(64), 0, st, jobs, prefix,
                                njobs, step, ttiles, remap);
+    }
+}
+
+// Resident blocks per CU of a step kernel (0 if the query fails).
+template <int M>
+static int occupancy_m(int ndim, int nw, bool adj)
+{
+    int n = 0;
+    hipError_t e = hipSuccess;
+    if (ndim == 3) {
+        if (nw == 8)
+            e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, true, 8>, 512, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, false, 8>, 512, 0);
+        else
+            e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, true, 4>, 256, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, false, 4>, 256, 0);
+    } else {
+        e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step2d<M, true>, 64, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step2d<M, false>, 64, 0);
+    }
+    return e == hipSuccess ? n : 0;
+}
+
+int step_blocks_per_cu(int ndim, int M, int nw, bool adj)
+{
+    switch (M) {
+    case 1: return occupancy_m<1>(ndim, nw, adj);
+    case 2: return occupancy_m<2>(ndim, nw, adj);
+    case 4: return occupancy_m<4>(ndim, nw, adj);
+    case 8: return occupancy_m<8>(ndim, nw, adj);
+    default: return 0;
     }
 }
 

@@ -42,6 +42,7 @@ void launch_fold(int ndim, const Job *jobs, int njobs, int M, int gy, int nz, in
                  int nb, int nzm, int nym, int nxm, float *tmp1, float *tmp2, const float *v,
                  float *dv, hipStream_t st);
 int vstats_blocks();
+int step_blocks_per_cu(int ndim, int M, int nw, bool adj);
 void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st);
 }  // namespace fwi
 
@@ -274,11 +275,25 @@ void tiles_for(const Geometry &g, int njobs, int *ntx, int *nty, int *nzc, int *
     *ntx = (g.nx + M + kTileX - 1) / kTileX;
     *nty = g.ndim == 3 ? (g.ny + ty - 1) / ty : 1;
     const int64_t per = (int64_t)(*ntx) * (*nty) * njobs;
-    // about four resident blocks per CU (256 CUs): fewer leaves the memory
-    // system idle, more only adds z-chunk warm-up planes
-    int64_t target = g.ndim == 3 ? 1024 : 8192;
+    // 3-D: as many z chunks as fill one wave of resident blocks of the forward
+    // step kernel (its occupancy times the CU count): fewer leave the memory
+    // system idle, more add z-chunk warm-up planes and a partial second wave.
+    // 2-D fields are small and cache-resident: many short chunks.
+    int64_t target = 8192;
+    if (g.ndim == 3) {
+        static int cus = 0;
+        if (cus == 0) {
+            int dev = 0;
+            hipDeviceProp_t prop;
+            if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+                cus = prop.multiProcessorCount;
+            if (cus <= 0) cus = 256;
+        }
+        const int occ = std::max(1, step_blocks_per_cu(3, g.M, waves3d(), false));
+        target = (int64_t)occ * cus;
+    }
     if (const char *e = getenv("FWI_TARGET_BLOCKS")) target = std::max(1, atoi(e));
-    int want = (int)std::max<int64_t>(1, (target + per - 1) / per);
+    int want = (int)std::max<int64_t>(1, g.ndim == 3 ? target / per : (target + per - 1) / per);
     int z = (g.nz + want - 1) / want;
     z = std::max(z, std::min(g.nz, std::max(2 * M, 8)));
     if (const char *e = getenv("FWI_ZCHUNK")) z = std::max(1, atoi(e));

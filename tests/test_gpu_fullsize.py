@@ -1,0 +1,78 @@
+"""Parity at the workloads' full sizes, in the launch configuration bench.py uses.
+
+* 2-D gradient workload (1024x320, 3000 steps): one shot's misfit and dv, and
+  a four-shot batched forward, element by element against the FP64 oracle.
+* 3-D forward workload (256^3 + sponge): the full grid and receiver plane
+  against the oracle over the first 100 steps (the oracle needs ~1 min).
+* 3-D revolve workload (512x512x256, 3000 steps, 40 GB snapshot budget): the
+  revolve gradient equals the every-50 gradient bitwise at full size (a
+  property that holds at any size: both recompute the same forward levels),
+  and the 64^3 crop run's gradient matches the oracle (600 steps, so that the
+  oracle finishes in seconds).
+"""
+import numpy as np
+import pytest
+
+from gpu_common import (cfg, dev, f32, gpu_forward, gpu_gradient, inputs, oracle_forward,
+                        oracle_gradient, rel_l2)
+from paper_1912_08063_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def test_c3_single_shot_gradient_full():
+    P = f32(wl.c3(nshots=32))
+    Q = wl.Problem(P.name, P.v, P.dx, P.dt, P.nt, P.order, P.nb, P.eta_max, P.wavelet[5:6],
+                   P.src_pos[5:6], P.rec_pos[5:6])
+    obs = np.asarray(oracle_forward(Q), np.float32).astype(np.float64)
+    v0 = np.asarray(P.v_start, np.float32).astype(np.float64)
+    mis_g, dv_g, tr_g = gpu_gradient(Q, v0, obs, "every:50")
+    mis_o, dv_o = oracle_gradient(Q, v0, obs)
+    assert abs(mis_g - mis_o) <= 1e-3 * mis_o
+    assert rel_l2(dv_g, dv_o) <= 1e-3, rel_l2(dv_g, dv_o)
+
+
+def test_c3_four_shot_batched_forward_full():
+    P = f32(wl.c3(nshots=32))
+    idx = [0, 11, 22, 31]
+    Q = wl.Problem(P.name, P.v, P.dx, P.dt, P.nt, P.order, P.nb, P.eta_max, P.wavelet[idx],
+                   P.src_pos[idx], P.rec_pos[idx])
+    g = gpu_forward(Q)
+    o = oracle_forward(Q)
+    for s in range(4):
+        assert rel_l2(g[s], o[s]) <= 1e-4
+
+
+def test_c2_full_grid_first_100_steps():
+    P = f32(wl.c2(nt=100))
+    g = gpu_forward(P)
+    o = oracle_forward(P)
+    assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
+
+
+def test_c5_revolve_equals_every_k_full_size():
+    import torch
+    from paper_1912_08063_amd import api
+    P = f32(wl.c5())
+    vt, w, s, r = inputs(P)
+    obs = api.forward(vt, w, s, r, cfg(P))
+    v0 = dev(P.v_start, torch.float32)
+    m1, dv1 = api.gradient(v0, obs, w, s, r, cfg(P, "revolve:40e9"))
+    torch.cuda.synchronize()
+    a = dv1.cpu().numpy()
+    del dv1
+    m2, dv2 = api.gradient(v0, obs, w, s, r, cfg(P, "every:50"))
+    torch.cuda.synchronize()
+    assert m1 == m2
+    assert np.array_equal(a, dv2.cpu().numpy())
+    assert np.all(np.isfinite(a)) and np.abs(a).max() > 0
+
+
+def test_c5_crop_gradient_vs_oracle():
+    P = f32(wl.c5_crop(nt=600))
+    obs = np.asarray(oracle_forward(P), np.float32).astype(np.float64)
+    v0 = np.asarray(P.v_start, np.float32).astype(np.float64)
+    mis_g, dv_g, _ = gpu_gradient(P, v0, obs, "revolve:6")
+    mis_o, dv_o = oracle_gradient(P, v0, obs)
+    assert abs(mis_g - mis_o) <= 1e-3 * mis_o
+    assert rel_l2(dv_g, dv_o) <= 1e-3, rel_l2(dv_g, dv_o)
