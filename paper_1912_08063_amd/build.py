@@ -21,7 +21,10 @@ DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 
 
-def build(verbose=False):
+def build(verbose=False, out=None, extra=None):
+    """Compile every source and link libfwi.so (or `out`).  `extra` (or the
+    environment variable FWI_HIPCC_FLAGS) adds compiler flags, e.g. -D options."""
+    extra = list(extra or []) + os.environ.get("FWI_HIPCC_FLAGS", "").split()
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
@@ -29,7 +32,7 @@ def build(verbose=False):
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
         if src.endswith(".hip"):
-            cmd = [HIPCC] + COMMON + DEVICE_FLAGS + ["-x", "hip", "-c", path, "-o", obj]
+            cmd = [HIPCC] + COMMON + DEVICE_FLAGS + extra + ["-x", "hip", "-c", path, "-o", obj]
         else:   # host-only C++ (HIP runtime API only)
             cmd = [HIPCC] + COMMON + ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include",
                                       "-c", path, "-o", obj]
@@ -37,13 +40,14 @@ def build(verbose=False):
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    lib = out or LIB
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

@@ -17,8 +17,8 @@
 namespace fwi {
 
 constexpr int kTileX = 64;   // memory columns per tile (one wavefront)
-constexpr int kRowsPerWave = 4;   // 3-D: y rows per thread (register blocking)
-// 3-D blocks hold 4 or 8 wavefronts: a tile is 64 (x) by kRowsPerWave * waves (y)
+// 3-D blocks hold 4 or 8 wavefronts of 64 lanes, each thread owning 2 or 4
+// consecutive y rows: a tile is 64 (x) by rows * wavefronts (y)
 constexpr int kGatherThreads = 256;
 
 struct Job {
@@ -31,9 +31,12 @@ struct Job {
     int64_t fstride;       // floats per field allocation
     float eta_dt;          // eta_max * dt / nb^2: eta*dt = eta_dt * sum_a d_a^2
     float src_scale;       // dt^2 / dx^D
-    // tiling of the step kernels
-    int32_t ntx, nty, nzc, zc;   // tiles in x and y, z chunks and chunk length
-    int32_t ntiles;              // ntx * nty * nzc
+    // tiling of the step kernels: tile[0] forward launches, tile[1] adjoint
+    // launches (their blocks may differ in shape)
+    struct Tiling {
+        int32_t ntx, nty, nzc, zc;   // tiles in x and y, z chunks and chunk length
+        int32_t ntiles;              // ntx * nty * nzc
+    } tile[2];
     int32_t ngather;             // gather blocks (forward record)
     // time: forward n = n0 + step, adjoint k = k0 - step; a launch updates a
     // job only for n in [fwd_lo, fwd_hi) (forward) or k in [adj_lo, adj_hi)

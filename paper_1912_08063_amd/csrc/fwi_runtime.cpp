@@ -225,7 +225,7 @@ void make_layout(const fwi_problem *p, const Geometry &g, const Policy &po, int 
     Carver w;
     L->kappa = w.take(fb);
     L->jobs = w.take(sizeof(Job) * (uint64_t)njobs);
-    L->prefix = w.take(sizeof(int) * 2ull * (njobs + 1));
+    L->prefix = w.take(sizeof(int) * 3ull * (njobs + 1));
     L->rec_off = w.take(sizeof(int64_t) * S * R + 8);
     L->rec_next = w.take(sizeof(int32_t) * S * R + 4);
     L->rec_head = w.take(sizeof(int32_t) * S * R + 4);
@@ -261,17 +261,27 @@ void make_layout(const fwi_problem *p, const Geometry &g, const Policy &po, int 
     L->ck_total = c.off;
 }
 
-// wavefronts per 3-D block (4 or 8)
-int waves3d()
+// 3-D block shape code: 4 (4 wavefronts, 4 rows per thread), 8 (8, 4) or
+// 42 (4 wavefronts, 2 rows per thread).  Forward launches default to 4; the
+// adjoint kernel, which carries two fields, to 42 (fewer registers per
+// thread, twice the resident waves).
+int shape_code(bool adj)
 {
-    if (const char *e = getenv("FWI_WAVES")) return atoi(e) == 8 ? 8 : 4;
-    return 4;
+    if (const char *e = getenv(adj ? "FWI_WAVES_ADJ" : "FWI_WAVES")) {
+        const int v = atoi(e);
+        if (v == 4 || v == 8 || v == 42) return v;
+    }
+    return adj ? 42 : 4;
 }
+int waves3d() { return shape_code(false); }
+int block_waves(int code) { return code == 8 ? 8 : 4; }
+int block_rows(int code) { return code == 42 ? 2 : 4; }
 
-void tiles_for(const Geometry &g, int njobs, int *ntx, int *nty, int *nzc, int *zc)
+void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *nzc, int *zc)
 {
     const int M = g.M;
-    const int ty = kRowsPerWave * waves3d();
+    const int code = shape_code(adj);
+    const int ty = block_rows(code) * block_waves(code);
     *ntx = (g.nx + M + kTileX - 1) / kTileX;
     *nty = g.ndim == 3 ? (g.ny + ty - 1) / ty : 1;
     const int64_t per = (int64_t)(*ntx) * (*nty) * njobs;
@@ -289,7 +299,7 @@ void tiles_for(const Geometry &g, int njobs, int *ntx, int *nty, int *nzc, int *
                 cus = prop.multiProcessorCount;
             if (cus <= 0) cus = 256;
         }
-        const int occ = std::max(1, step_blocks_per_cu(3, g.M, waves3d(), false));
+        const int occ = std::max(1, step_blocks_per_cu(3, g.M, code, adj));
         target = (int64_t)occ * cus;
     }
     if (const char *e = getenv("FWI_TARGET_BLOCKS")) target = std::max(1, atoi(e));
@@ -302,7 +312,7 @@ void tiles_for(const Geometry &g, int njobs, int *ntx, int *nty, int *nzc, int *
     *nzc = (g.nz + z - 1) / z;
 }
 
-int gather_threads(const Geometry &g) { return g.ndim == 3 ? 64 * waves3d() : 64; }
+int gather_threads(const Geometry &g) { return g.ndim == 3 ? 64 * block_waves(waves3d()) : 64; }
 
 // ------------------------------------------------------------ call context
 struct Ctx {
@@ -316,9 +326,9 @@ struct Ctx {
     std::vector<Job> jobs;
     Job *d_jobs = nullptr;
     int *d_prefix = nullptr;
-    int ttiles = 0, gblocks = 0, gthreads = 64;
+    int ttiles = 0, atiles = 0, gblocks = 0, gthreads = 64;
     int remap = 1;
-    int nw = 4;
+    int nw = 4, nw_adj = 42;
     std::vector<int> slot_time;
 
     float *f_at(uint64_t off, bool in_ws) const
@@ -354,7 +364,8 @@ int prepare(Ctx &c, const fwi_problem *p, int mode, const fwi_ckpt *ck, void *ws
     c.ck = static_cast<char *>(ckbuf);
     c.st = static_cast<hipStream_t>(stream);
     if (const char *e = getenv("FWI_XCD_REMAP")) c.remap = atoi(e) != 0;
-    c.nw = waves3d();
+    c.nw = shape_code(false);
+    c.nw_adj = shape_code(true);
     return FWI_OK;
 }
 
@@ -426,8 +437,11 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
     }
 
     // job table: one job per shot
-    int ntx, nty, nzc, zc;
-    tiles_for(g, S, &ntx, &nty, &nzc, &zc);
+    Job::Tiling til[2];
+    for (int a = 0; a < 2; ++a) {
+        tiles_for(g, S, a == 1, &til[a].ntx, &til[a].nty, &til[a].nzc, &til[a].zc);
+        til[a].ntiles = til[a].ntx * til[a].nty * til[a].nzc;
+    }
     c.gthreads = gather_threads(g);
     const int ng = (R + c.gthreads - 1) / c.gthreads;
     const uint64_t fs = (uint64_t)g.fstride;
@@ -442,7 +456,8 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
     double cell = 1.0;
     for (int a = 0; a < D; ++a) cell *= p->dx;
     c.jobs.assign(S, Job{});
-    std::vector<int> prefix(2 * (S + 1), 0);
+    // [forward tile prefix | gather prefix | adjoint tile prefix], S+1 each
+    std::vector<int> prefix(3 * (S + 1), 0);
     for (int s = 0; s < S; ++s) {
         Job &J = c.jobs[s];
         J.nz = g.nz; J.ny = g.ny; J.nx = g.nx;
@@ -450,8 +465,8 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
         J.plane = g.plane; J.fstride = g.fstride;
         J.eta_dt = g.nb > 0 ? (float)((double)p->eta_max * p->dt / ((double)g.nb * g.nb)) : 0.f;
         J.src_scale = (float)((double)p->dt * p->dt / cell);
-        J.ntx = ntx; J.nty = nty; J.nzc = nzc; J.zc = zc;
-        J.ntiles = ntx * nty * nzc;
+        J.tile[0] = til[0];
+        J.tile[1] = til[1];
         J.ngather = ng;
         J.n0 = 0; J.k0 = 0; J.nt = p->nt;
         J.fwd_lo = 0; J.fwd_hi = p->nt;
@@ -475,11 +490,13 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
         J.rec_head = d_rhead + (size_t)s * R;
         J.traces = traces ? traces + (size_t)s * p->nt * R : nullptr;
         J.res = res ? res + (size_t)s * p->nt * R : nullptr;
-        prefix[s + 1] = prefix[s] + J.ntiles;
+        prefix[s + 1] = prefix[s] + J.tile[0].ntiles;
         prefix[S + 1 + s + 1] = prefix[S + 1 + s] + ng;
+        prefix[2 * (S + 1) + s + 1] = prefix[2 * (S + 1) + s] + J.tile[1].ntiles;
     }
     c.ttiles = prefix[S];
     c.gblocks = prefix[2 * S + 1];
+    c.atiles = prefix[3 * S + 2];
     c.d_jobs = reinterpret_cast<Job *>(c.ws + c.L.jobs);
     c.d_prefix = reinterpret_cast<int *>(c.ws + c.L.prefix);
     HIP_TRY(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(Job) * S, hipMemcpyHostToDevice, c.st));
@@ -509,8 +526,8 @@ int fwd_step(Ctx &c, int n, bool record)
 
 int adj_step(Ctx &c, int k)
 {
-    launch_step(c.g.ndim, c.g.M, c.nw, true, c.d_jobs, c.d_prefix, c.p->nshots, -k, c.ttiles, 0,
-                c.remap, c.st);
+    launch_step(c.g.ndim, c.g.M, c.nw_adj, true, c.d_jobs, c.d_prefix + 2 * (c.p->nshots + 1),
+                c.p->nshots, -k, c.atiles, 0, c.remap, c.st);
     launch_adj_inject(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
                       c.gthreads, -k, c.st);
     return FWI_OK;
@@ -1072,11 +1089,12 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
             }
             const bool finished = o.type == JOP_FWD ? o.a >= o.b : o.a < o.b;
             if (finished) ++J->head;
-            Group &g = group_of(J->c.g.ndim, J->c.g.M, o.type == JOP_ADJ, J->c.nw);
+            const bool isadj = o.type == JOP_ADJ;
+            Group &g = group_of(J->c.g.ndim, J->c.g.M, isadj, isadj ? J->c.nw_adj : J->c.nw);
             g.steps = std::max(g.steps, steps);
             g.gthreads = J->c.gthreads;
             g.table.push_back(t);
-            g.tp.push_back(g.tp.back() + t.ntiles);
+            g.tp.push_back(g.tp.back() + t.tile[isadj ? 1 : 0].ntiles);
             g.gp.push_back(g.gp.back() + ((o.type == JOP_FWD && t.record) || o.type == JOP_ADJ
                                               ? t.ngather : 0));
         }
