@@ -265,22 +265,23 @@ void make_layout(const fwi_problem *p, const Geometry &g, const Policy &po, int 
 // 42 (4 wavefronts, 2 rows per thread).  Forward launches default to 4; the
 // adjoint kernel, which carries two fields, to 42 (fewer registers per
 // thread, twice the resident waves).
-int shape_code(bool adj)
+// The 16th-order stencil (M = 8) needs twice the queue: 2 rows per thread
+// in both directions.
+int shape_code(bool adj, int M)
 {
     if (const char *e = getenv(adj ? "FWI_WAVES_ADJ" : "FWI_WAVES")) {
         const int v = atoi(e);
         if (v == 4 || v == 8 || v == 42) return v;
     }
-    return adj ? 42 : 4;
+    return adj || M >= 8 ? 42 : 4;
 }
-int waves3d() { return shape_code(false); }
 int block_waves(int code) { return code == 8 ? 8 : 4; }
 int block_rows(int code) { return code == 42 ? 2 : 4; }
 
 void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *nzc, int *zc)
 {
     const int M = g.M;
-    const int code = shape_code(adj);
+    const int code = shape_code(adj, g.M);
     const int ty = block_rows(code) * block_waves(code);
     *ntx = (g.nx + M + kTileX - 1) / kTileX;
     *nty = g.ndim == 3 ? (g.ny + ty - 1) / ty : 1;
@@ -312,7 +313,10 @@ void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *
     *nzc = (g.nz + z - 1) / z;
 }
 
-int gather_threads(const Geometry &g) { return g.ndim == 3 ? 64 * block_waves(waves3d()) : 64; }
+int gather_threads(const Geometry &g)
+{
+    return g.ndim == 3 ? 64 * block_waves(shape_code(false, g.M)) : 64;
+}
 
 // ------------------------------------------------------------ call context
 struct Ctx {
@@ -364,8 +368,8 @@ int prepare(Ctx &c, const fwi_problem *p, int mode, const fwi_ckpt *ck, void *ws
     c.ck = static_cast<char *>(ckbuf);
     c.st = static_cast<hipStream_t>(stream);
     if (const char *e = getenv("FWI_XCD_REMAP")) c.remap = atoi(e) != 0;
-    c.nw = shape_code(false);
-    c.nw_adj = shape_code(true);
+    c.nw = shape_code(false, c.g.M);
+    c.nw_adj = shape_code(true, c.g.M);
     return FWI_OK;
 }
 

@@ -124,7 +124,7 @@ class Server:
     """Admission by HBM footprint, resident job state, continuous batching."""
 
     def __init__(self, device="cuda", hbm_budget=None, max_active=64, chunk=50,
-                 keep_outputs=False):
+                 keep_outputs=False, fill_cells=24_000_000):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -135,6 +135,10 @@ class Server:
         self.max_active = int(max_active)
         self.chunk = int(chunk)
         self.keep = keep_outputs
+        # co-schedule jobs only while their padded cells per step stay below
+        # what saturates the GPU: small jobs batch, a big job runs (nearly)
+        # alone instead of slowing every other job down
+        self.fill_cells = fill_cells
         self.ws = None
 
     # ---------------------------------------------------------------- sizes
@@ -214,6 +218,7 @@ class Server:
                 raise ValueError("gradient request %d has no observed data" % r.rid)
         active, results = [], []
         used = 0
+        cells = 0
         stream = torch.cuda.current_stream(self.device).cuda_stream
         ws_bytes = _lib.fwi_jobs_ws_bytes(self.max_active)
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
@@ -232,12 +237,15 @@ class Server:
                 need = self.footprint(r)
                 if used + need > self.budget and active:
                     break
+                if self.fill_cells and active and cells + r.problem.padded_cells > self.fill_cells:
+                    break
                 if need > self.budget:
                     raise MemoryError("request %d needs %d bytes > budget %d" %
                                       (r.rid, need, self.budget))
                 pending.pop(0)
                 a = self._admit(r, now)
                 used += a.footprint
+                cells += r.problem.padded_cells
                 active.append(a)
             if not active:
                 if realtime and pending:
@@ -256,9 +264,10 @@ class Server:
                 if done:
                     results.append(self._finish(a, now))
                     used -= a.footprint
-                    if log:
-                        log("request %d (%s) done: latency %.3f s" % (a.req.rid, a.req.kind,
-                                                                      results[-1].latency))
+                    cells -= a.req.problem.padded_cells
+                    if log and len(results) % 10 == 0:
+                        log("%d requests done (last: %d, %s, latency %.3f s)" % (
+                            len(results), a.req.rid, a.req.kind, results[-1].latency))
                 else:
                     still.append(a)
             active = still
@@ -266,7 +275,8 @@ class Server:
         lat = np.array([r.latency for r in results])
         report = {
             "requests": len(results), "chunks": chunks, "chunk_steps": self.chunk,
-            "max_active": self.max_active, "makespan_s": makespan,
+            "max_active": self.max_active, "fill_cells": self.fill_cells,
+            "makespan_s": makespan,
             "shots_per_s": len(results) / makespan if makespan > 0 else None,
             "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
@@ -288,27 +298,35 @@ def main(argv=None):
     ap.add_argument("--skip-plain", action="store_true")
     args = ap.parse_args(argv)
     log = lambda m: print("[serve] " + m, file=sys.stderr, flush=True)
-    reqs = make_stream(args.requests, 1.0, args.seed, args.scale)
+    reqs = []
+    for i in range(args.requests):   # generated one by one, with progress
+        kind, P = make_request_problem(i, args.seed, args.scale)
+        reqs.append(Request(i, kind, 0.0, P))
+        if (i + 1) % 20 == 0:
+            log("generated %d requests" % (i + 1))
     log("observed data for %d gradient requests" % sum(r.kind == "gradient" for r in reqs))
-    attach_observed(reqs)
+    for i in range(0, len(reqs), 20):
+        attach_observed(reqs[i:i + 20])
+        log("observed data up to request %d" % min(i + 20, len(reqs)))
     rate = args.rate
     out = {}
     if rate is None:
         # saturated throughput: everything arrives at t = 0
         for r in reqs:
             r.arrival = 0.0
-        _, sat = Server(max_active=args.max_active, chunk=args.chunk).run(reqs, realtime=True)
+        _, sat = Server(max_active=args.max_active, chunk=args.chunk).run(reqs, realtime=True,
+                                                                        log=log)
         out["saturated"] = sat
         rate = 0.8 * sat["shots_per_s"]
         log("saturated: %.2f shots/s" % sat["shots_per_s"])
     arr = np.cumsum(np.random.default_rng(args.seed).exponential(1.0 / rate, len(reqs)))
     for r, t in zip(reqs, arr):
         r.arrival = float(t)
-    _, rep = Server(max_active=args.max_active, chunk=args.chunk).run(reqs, realtime=True)
+    _, rep = Server(max_active=args.max_active, chunk=args.chunk).run(reqs, realtime=True, log=log)
     out["batched"] = dict(rep, rate=rate)
     log("batched: p50 %.3f s p99 %.3f s" % (rep["p50_latency_s"], rep["p99_latency_s"]))
     if not args.skip_plain:
-        _, rep1 = Server(max_active=1, chunk=args.chunk).run(reqs, realtime=True)
+        _, rep1 = Server(max_active=1, chunk=args.chunk).run(reqs, realtime=True, log=log)
         out["plain"] = dict(rep1, rate=rate)
         log("plain: p50 %.3f s p99 %.3f s" % (rep1["p50_latency_s"], rep1["p99_latency_s"]))
     print(json.dumps(out), flush=True)

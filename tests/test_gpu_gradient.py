@@ -37,8 +37,10 @@ def test_gradient_2d(order):
     _check(P, obs, v0, "every:25")
 
 
-def test_gradient_3d():
-    P, obs, v0 = _setup(wl.small_3d(shape=(26, 22, 75), nt=90, nshots=2, nrec=30), 1.5)
+@pytest.mark.parametrize("order", [8, 16])
+def test_gradient_3d(order):
+    P, obs, v0 = _setup(wl.small_3d(shape=(26, 22, 75), nt=90, order=order, nshots=2, nrec=30),
+                        1.5)
     _check(P, obs, v0, "revolve:4")
 
 
@@ -126,3 +128,21 @@ def test_autograd_matches_central_differences():
     h = 2.0   # m/s
     fd = (phi(v0 + h * direction) - phi(v0 - h * direction)) / (2 * h)
     assert abs(fd - an) <= 1e-2 * abs(an), (fd, an)
+
+
+def test_lbfgs_reduces_the_misfit():
+    """A few L-BFGS iterations driven by fwi_gradient lower the misfit and move
+    the model towards the truth (a smooth start, sponge held fixed)."""
+    import torch
+    from paper_1912_08063_amd import api, inversion
+    P = f32(wl.small_2d(nz=40, nx=96, nt=260, nshots=4, nrec=48))
+    vt, w, s, r = inputs(P)
+    c = cfg(P, "every:20")
+    obs = api.forward(vt, w, s, r, c)
+    v0 = dev(wl.smooth(P.v, 4.0), torch.float32)
+    v, hist = inversion.lbfgs(v0, obs, w, s, r, c, iters=4, vmin=float(P.v.min()) - 100,
+                              vmax=float(P.v.max()) + 100)
+    assert len(hist) >= 3
+    assert all(b < a for a, b in zip(hist, hist[1:]))
+    assert hist[-1] < 0.5 * hist[0]
+    assert float((v - vt).norm()) < float((v0 - vt).norm())
