@@ -98,7 +98,17 @@ __device__ __forceinline__ float leapfrog(float val, float prev, int d2, float e
 // new level, the gradient accumulator) are non-temporal, leaving L2 to the
 // rows that neighbouring tiles share (+4 % on the 3-D forward step).
 // FWI_STREAM_CACHED at build time restores ordinary accesses.
-__device__ __forceinline__ float ld_stream(const float *p)
+// Field pointers come from the job table, so the compiler cannot see that
+// they address global memory; without the cast every access would be a
+// flat load (64-bit address arithmetic per access, and flat loads also hold
+// the LDS counter, so each LDS wait would wait for the prefetches too).
+#define GMEM __attribute__((address_space(1)))
+typedef GMEM float gfloat;
+
+__device__ __forceinline__ const gfloat *gptr(const float *p) { return (const gfloat *)p; }
+__device__ __forceinline__ gfloat *gptr(float *p) { return (gfloat *)p; }
+
+__device__ __forceinline__ float ld_stream(const gfloat *p)
 {
 #ifdef FWI_STREAM_CACHED
     return *p;
@@ -106,7 +116,7 @@ __device__ __forceinline__ float ld_stream(const float *p)
     return __builtin_nontemporal_load(p);
 #endif
 }
-__device__ __forceinline__ void st_stream(float *p, float v)
+__device__ __forceinline__ void st_stream(gfloat *p, float v)
 {
 #ifdef FWI_STREAM_CACHED
     *p = v;
@@ -115,10 +125,50 @@ __device__ __forceinline__ void st_stream(float *p, float v)
 #endif
 }
 
+// Plane accesses go through a buffer resource (base and size of one plane in
+// scalar registers) and a 32-bit per-lane byte offset: no per-lane address
+// arithmetic, and an offset past the plane reads zero instead of faulting.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit buffer, CDNA
+constexpr int kCacheNT = 2;              // non-temporal cache policy
+
+__device__ __forceinline__ rsrc_t plane_rsrc(const gfloat *f, int zmem, int64_t plane,
+                                             int pbytes)
+{
+    const float *p = (const float *)(f + (int64_t)zmem * plane);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), 0, pbytes, kRsrcWord3);
+}
+__device__ __forceinline__ float ldb(rsrc_t r, uint32_t boff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, 0));
+}
+__device__ __forceinline__ float ldb_stream(rsrc_t r, uint32_t boff)
+{
+#ifdef FWI_STREAM_CACHED
+    return ldb(r, boff);
+#else
+    return __builtin_bit_cast(float,
+                              __builtin_amdgcn_raw_buffer_load_b32(r, (int)boff, 0, kCacheNT));
+#endif
+}
+__device__ __forceinline__ void stb_stream(rsrc_t r, uint32_t boff, float v)
+{
+#ifdef FWI_STREAM_CACHED
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)boff, 0, 0);
+#else
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)boff, 0,
+                                          kCacheNT);
+#endif
+}
+
 // Plane of a field: element (z, row, col) is at base[(z + M) * plane + row_offset].
 // The plane base is uniform across the block (scalar registers); per-thread
 // offsets within a plane are 32-bit, so every load is base + 32-bit offset.
-__device__ __forceinline__ const float *plane_ptr(const float *f, int zmem, int64_t plane)
+__device__ __forceinline__ const gfloat *plane_ptr(const gfloat *f, int zmem, int64_t plane)
+{
+    return f + (int64_t)zmem * plane;
+}
+__device__ __forceinline__ gfloat *plane_ptr(gfloat *f, int zmem, int64_t plane)
 {
     return f + (int64_t)zmem * plane;
 }
@@ -174,45 +224,51 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     const int tz = local / T.nty;
     const int z0 = tz * T.zc, z1 = min(z0 + T.zc, nz);
 
-    const float *cur, *prv;
-    float *out;
-    const float *fwd = nullptr;
-    float *grad = nullptr;
+    const gfloat *cur, *prv;
+    gfloat *out;
+    const gfloat *fwd = nullptr;
+    gfloat *grad = nullptr;
     bool accum = false;
     if constexpr (ADJ) {
-        cur = J->adj + (int64_t)((n + 1) & 1) * fstride;
-        prv = J->adj + (int64_t)(n & 1) * fstride;
-        out = J->adj + (int64_t)(n & 1) * fstride;
+        cur = gptr(J->adj) + (int64_t)((n + 1) & 1) * fstride;
+        prv = gptr(J->adj) + (int64_t)(n & 1) * fstride;
+        out = gptr(J->adj) + (int64_t)(n & 1) * fstride;
         accum = J->accumulate && n <= J->nt - 1;
-        fwd = J->ring + (int64_t)mod_pos(n, J->R) * fstride;
-        grad = J->grad;
+        fwd = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
+        grad = gptr(J->grad);
     } else {
-        cur = J->ring + (int64_t)mod_pos(n, J->R) * fstride;
-        prv = J->ring + (int64_t)mod_pos(n - 1, J->R) * fstride;
-        out = J->ring + (int64_t)mod_pos(n + 1, J->R) * fstride;
+        cur = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
+        prv = gptr(J->ring) + (int64_t)mod_pos(n - 1, J->R) * fstride;
+        out = gptr(J->ring) + (int64_t)mod_pos(n + 1, J->R) * fstride;
     }
-    const float *kap = J->kappa;
+    const gfloat *kap = gptr(J->kappa);
     const float eta_dt = J->eta_dt;
+    const int pbytes = (int)(plane * (int64_t)sizeof(float));
 
     // ---- per-thread geometry (loop invariant)
     const int lane = tid & 63, wv = tid >> 6;
     const int col = tx * TX + lane;   // memory column
     const int x = col - M;            // padded-grid x
     const bool ax = x >= 0 && x < nx;
+    // Loads are unconditional: a row past the frame is clamped to the last
+    // frame row and a column outside the row to its edge.  Both hold zeros
+    // (frames and row padding are zero-filled and never written), exactly
+    // the values a masked load would give, and no active cell reads them
+    // beyond that.  Stores stay masked.
+    const int last_row = ny + 2 * M - 1;   // memory rows per plane - 1
     bool act[RY];
-    uint32_t roff[RY];
+    uint32_t roff[RY];   // byte offsets within a plane
     int dxy2[RY];
     const int dxs = sponge_depth(x, nx, nb);
 #pragma unroll
     for (int i = 0; i < RY; ++i) {
         const int yy = ty * TY + wv * RY + i;
         act[i] = ax && yy < ny;
-        roff[i] = (uint32_t)((yy + M) * pitch + col);
+        roff[i] = 4u * (uint32_t)(min(yy + M, last_row) * pitch + col);
         const int d = sponge_depth(yy, ny, nb);
         dxy2[i] = d * d + dxs * dxs;
     }
     uint32_t hyo[NYH], hxo[NXH];
-    bool hyv[NYH], hxv[NXH];
     int hyl[NYH], hxl[NXH];
 #pragma unroll
     for (int q = 0; q < NYH; ++q) {   // rows above and below the tile
@@ -220,8 +276,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         const int r = (h / TX) % (2 * M), c = h % TX;
         const int ly = r < M ? r : r + TY;
         const int yg = ty * TY - M + ly;
-        hyv[q] = h < 2 * M * TX && yg < ny + M;
-        hyo[q] = (uint32_t)((yg + M) * pitch + tx * TX + c);
+        hyo[q] = 4u * (uint32_t)(min(yg + M, last_row) * pitch + tx * TX + c);
         hyl[q] = h < 2 * M * TX ? ly * LX + M + c : -1;
     }
 #pragma unroll
@@ -229,10 +284,9 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         const int h = tid + NT * q;
         const int r = (h / (2 * M)) % TY, c = h % (2 * M);
         const int lc = c < M ? c : c + TX;
-        const int cm = tx * TX - M + lc;
+        const int cm = min(max(tx * TX - M + lc, 0), pitch - 1);
         const int yg = ty * TY + r;
-        hxv[q] = h < TY * 2 * M && cm >= 0 && cm < pitch && yg < ny + M;
-        hxo[q] = (uint32_t)((yg + M) * pitch + cm);
+        hxo[q] = 4u * (uint32_t)(min(yg + M, last_row) * pitch + cm);
         hxl[q] = h < TY * 2 * M ? (M + r) * LX + lc : -1;
     }
     // source (forward): the block that owns it adds it at its plane
@@ -254,35 +308,35 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         // halo ring: slot s holds the halos of plane z0 - M + s (s = M+1 .. 2M now)
 #pragma unroll
         for (int s = M + 1; s < Q; ++s) {
-            const float *ph = plane_ptr(cur, z0 + s, plane);
+            const rsrc_t ph = plane_rsrc(cur, z0 + s, plane, pbytes);
 #pragma unroll
-            for (int h = 0; h < NYH; ++h) hy[h][s] = hyv[h] ? ph[hyo[h]] : 0.f;
+            for (int h = 0; h < NYH; ++h) hy[h][s] = ldb(ph, hyo[h]);
 #pragma unroll
-            for (int h = 0; h < NXH; ++h) hx[h][s] = hxv[h] ? ph[hxo[h]] : 0.f;
+            for (int h = 0; h < NXH; ++h) hx[h][s] = ldb(ph, hxo[h]);
         }
     }
 #pragma unroll
     for (int s = 0; s < Q; ++s) {
-        const float *pc = plane_ptr(cur, z0 + s, plane);   // grid plane z0 - M + s
-        const float *pf = ADJ ? plane_ptr(fwd, z0 + s, plane) : nullptr;
+        const rsrc_t pc = plane_rsrc(cur, z0 + s, plane, pbytes);   // grid plane z0 - M + s
+        const rsrc_t pf = plane_rsrc(fwd, z0 + s, plane, pbytes);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            q[i][s] = act[i] ? pc[roff[i]] : 0.f;
-            if constexpr (ADJ) f[i][s] = act[i] ? pf[roff[i]] : 0.f;
+            q[i][s] = ldb(pc, roff[i]);
+            if constexpr (ADJ) f[i][s] = ldb(pf, roff[i]);
         }
     }
     float kv[RY], pv[RY], gv[ADJ ? RY : 1];
     {
-        const float *pk = plane_ptr(kap, z0 + M, plane);
-        const float *pp = plane_ptr(prv, z0 + M, plane);
+        const rsrc_t pk = plane_rsrc(kap, z0 + M, plane, pbytes);
+        const rsrc_t pp = plane_rsrc(prv, z0 + M, plane, pbytes);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            kv[i] = act[i] ? pk[roff[i]] : 0.f;
-            pv[i] = act[i] ? pp[roff[i]] : 0.f;
-            if constexpr (ADJ) gv[i] = act[i] && accum ? plane_ptr(grad, z0 + M, plane)[roff[i]] : 0.f;
+            kv[i] = ldb(pk, roff[i]);
+            pv[i] = ldb(pp, roff[i]);
+            if constexpr (ADJ) gv[i] = accum ? ldb(plane_rsrc(grad, z0 + M, plane, pbytes), roff[i]) : 0.f;
         }
-        const float *pc = plane_ptr(cur, z0 + M, plane);
-        const float *pf = ADJ ? plane_ptr(fwd, z0 + M, plane) : nullptr;
+        const rsrc_t pc = plane_rsrc(cur, z0 + M, plane, pbytes);
+        const rsrc_t pf = plane_rsrc(fwd, z0 + M, plane, pbytes);
         float *L = sp + (z0 & 1) * LS;
         float *LF = ADJ ? sf + (z0 & 1) * LS : nullptr;
 #pragma unroll
@@ -293,14 +347,14 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
 #pragma unroll
         for (int h = 0; h < NYH; ++h)
             if (hyl[h] >= 0) {
-                L[hyl[h]] = hyv[h] ? pc[hyo[h]] : 0.f;
-                if constexpr (ADJ) LF[hyl[h]] = hyv[h] ? pf[hyo[h]] : 0.f;
+                L[hyl[h]] = ldb(pc, hyo[h]);
+                if constexpr (ADJ) LF[hyl[h]] = ldb(pf, hyo[h]);
             }
 #pragma unroll
         for (int h = 0; h < NXH; ++h)
             if (hxl[h] >= 0) {
-                L[hxl[h]] = hxv[h] ? pc[hxo[h]] : 0.f;
-                if constexpr (ADJ) LF[hxl[h]] = hxv[h] ? pf[hxo[h]] : 0.f;
+                L[hxl[h]] = ldb(pc, hxo[h]);
+                if constexpr (ADJ) LF[hxl[h]] = ldb(pf, hxo[h]);
             }
     }
     __syncthreads();
@@ -315,41 +369,41 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             float nq[RY], nk[RY], np[RY], nhy[NYH], nhx[NXH];
             float nfq[ADJ ? RY : 1], ng[ADJ ? RY : 1], nfy[ADJ ? NYH : 1], nfx[ADJ ? NXH : 1];
             if (more) {
-                const float *pq = plane_ptr(cur, z + 1 + 2 * M, plane);
-                const float *pk = plane_ptr(kap, z + 1 + M, plane);
-                const float *pp = plane_ptr(prv, z + 1 + M, plane);
-                const float *ph = plane_ptr(cur, z + 1 + M, plane);
+                const rsrc_t pq = plane_rsrc(cur, z + 1 + 2 * M, plane, pbytes);
+                const rsrc_t pk = plane_rsrc(kap, z + 1 + M, plane, pbytes);
+                const rsrc_t pp = plane_rsrc(prv, z + 1 + M, plane, pbytes);
+                const rsrc_t ph = plane_rsrc(cur, z + 1 + M, plane, pbytes);
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
-                    nq[i] = act[i] ? pq[roff[i]] : 0.f;
-                    nk[i] = act[i] ? ld_stream(pk + roff[i]) : 0.f;
-                    np[i] = act[i] ? ld_stream(pp + roff[i]) : 0.f;
+                    nq[i] = ldb(pq, roff[i]);
+                    nk[i] = ldb_stream(pk, roff[i]);
+                    np[i] = ldb_stream(pp, roff[i]);
                 }
-                const float *phq = HQ ? plane_ptr(cur, z + 1 + 2 * M, plane) : ph;
+                const rsrc_t phq = HQ ? plane_rsrc(cur, z + 1 + 2 * M, plane, pbytes) : ph;
 #pragma unroll
-                for (int h = 0; h < NYH; ++h) nhy[h] = hyv[h] ? phq[hyo[h]] : 0.f;
+                for (int h = 0; h < NYH; ++h) nhy[h] = ldb(phq, hyo[h]);
 #pragma unroll
-                for (int h = 0; h < NXH; ++h) nhx[h] = hxv[h] ? phq[hxo[h]] : 0.f;
+                for (int h = 0; h < NXH; ++h) nhx[h] = ldb(phq, hxo[h]);
                 if constexpr (ADJ) {
-                    const float *fq = plane_ptr(fwd, z + 1 + 2 * M, plane);
-                    const float *fh = plane_ptr(fwd, z + 1 + M, plane);
-                    const float *pg = plane_ptr(grad, z + 1 + M, plane);
+                    const rsrc_t fq = plane_rsrc(fwd, z + 1 + 2 * M, plane, pbytes);
+                    const rsrc_t fh = plane_rsrc(fwd, z + 1 + M, plane, pbytes);
+                    const rsrc_t pg = plane_rsrc(grad, z + 1 + M, plane, pbytes);
 #pragma unroll
                     for (int i = 0; i < RY; ++i) {
-                        nfq[i] = act[i] ? fq[roff[i]] : 0.f;
-                        ng[i] = act[i] && accum ? ld_stream(pg + roff[i]) : 0.f;
+                        nfq[i] = ldb(fq, roff[i]);
+                        ng[i] = accum ? ldb_stream(pg, roff[i]) : 0.f;
                     }
 #pragma unroll
-                    for (int h = 0; h < NYH; ++h) nfy[h] = hyv[h] ? fh[hyo[h]] : 0.f;
+                    for (int h = 0; h < NYH; ++h) nfy[h] = ldb(fh, hyo[h]);
 #pragma unroll
-                    for (int h = 0; h < NXH; ++h) nfx[h] = hxv[h] ? fh[hxo[h]] : 0.f;
+                    for (int h = 0; h < NXH; ++h) nfx[h] = ldb(fh, hxo[h]);
                 }
             }
             // ---- plane z
             const float *L = sp + (z & 1) * LS;
             const float *LF = ADJ ? sf + (z & 1) * LS : nullptr;
-            float *po = const_cast<float *>(plane_ptr(out, z + M, plane));
-            float *pg = ADJ ? const_cast<float *>(plane_ptr(grad, z + M, plane)) : nullptr;
+            const rsrc_t po = plane_rsrc(out, z + M, plane, pbytes);
+            const rsrc_t pg = plane_rsrc(grad, z + M, plane, pbytes);
             const int dz = sponge_depth(z, nz, nb);
             float res[RY];
 #pragma unroll
@@ -372,7 +426,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             }
 #pragma unroll
             for (int i = 0; i < RY; ++i)
-                if (act[i]) st_stream(po + roff[i], leapfrog(res[i], pv[i], dxy2[i] + dz * dz, eta_dt));
+                if (act[i]) stb_stream(po, roff[i], leapfrog(res[i], pv[i], dxy2[i] + dz * dz, eta_dt));
             if constexpr (ADJ) {
                 if (accum) {
 #pragma unroll
@@ -388,7 +442,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                                 ((f[i][(k + M + m) % Q] - fc) + (f[i][(k + M - m) % Q] - fc));
                             lf = fmaf(W.c[m], d, lf);
                         }
-                        if (act[i]) st_stream(pg + roff[i], fmaf(q[i][(k + M) % Q], lf, gv[i]));
+                        if (act[i]) stb_stream(pg, roff[i], fmaf(q[i][(k + M) % Q], lf, gv[i]));
                     }
                 }
             }
@@ -475,24 +529,24 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
     const int tz = local / T.ntx;
     const int z0 = tz * T.zc, z1 = min(z0 + T.zc, nz);
 
-    const float *cur, *prv;
-    float *out;
-    const float *fwd = nullptr;
-    float *grad = nullptr;
+    const gfloat *cur, *prv;
+    gfloat *out;
+    const gfloat *fwd = nullptr;
+    gfloat *grad = nullptr;
     bool accum = false;
     if constexpr (ADJ) {
-        cur = J->adj + (int64_t)((n + 1) & 1) * fstride;
-        prv = J->adj + (int64_t)(n & 1) * fstride;
-        out = J->adj + (int64_t)(n & 1) * fstride;
+        cur = gptr(J->adj) + (int64_t)((n + 1) & 1) * fstride;
+        prv = gptr(J->adj) + (int64_t)(n & 1) * fstride;
+        out = gptr(J->adj) + (int64_t)(n & 1) * fstride;
         accum = J->accumulate && n <= J->nt - 1;
-        fwd = J->ring + (int64_t)mod_pos(n, J->R) * fstride;
-        grad = J->grad;
+        fwd = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
+        grad = gptr(J->grad);
     } else {
-        cur = J->ring + (int64_t)mod_pos(n, J->R) * fstride;
-        prv = J->ring + (int64_t)mod_pos(n - 1, J->R) * fstride;
-        out = J->ring + (int64_t)mod_pos(n + 1, J->R) * fstride;
+        cur = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
+        prv = gptr(J->ring) + (int64_t)mod_pos(n - 1, J->R) * fstride;
+        out = gptr(J->ring) + (int64_t)mod_pos(n + 1, J->R) * fstride;
     }
-    const float *kap = J->kappa;
+    const gfloat *kap = gptr(J->kappa);
     const float eta_dt = J->eta_dt;
 
     const int col = tx * TX + lane;

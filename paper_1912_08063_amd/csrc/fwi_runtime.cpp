@@ -124,6 +124,9 @@ int make_geometry(const fwi_problem *p, Geometry *g)
     g->fstride = (int64_t)(g->nz + 2 * g->M) * g->plane;
     g->model_cells = (int64_t)g->nzm * g->nym * g->nxm;
     if (g->fstride > (int64_t(1) << 40)) return fail(FWI_EINVAL, "grid too large");
+    // the step kernels address a plane with 32-bit byte offsets
+    if (g->plane * (int64_t)sizeof(float) >= (int64_t(1) << 31))
+        return fail(FWI_EINVAL, "grid plane too large");
     return FWI_OK;
 }
 
