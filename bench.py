@@ -35,7 +35,7 @@ def recorded_traffic():
     """HBM bytes per step launch from the rocprofv3 counter runs recorded in
     profiles/, or None if the kernel or runtime source changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_k_step3d_fwd_c2.json")
+    path = os.path.join(ROOT, "profiles", "traffic_k_step3d_fwd_layered304.json")
     try:
         rec = json.load(open(path))
         for src, digest in rec["sources_sha1"].items():
@@ -61,13 +61,13 @@ def cpu_baseline(P, nt_sample):
 
 
 def gradient_section(dev, nt, shots, every):
-    """C3: 2-D FWI gradient, 32 shots.  Batched: one fwi_gradient call for all
+    """2-D FWI gradient, 1024x320 model, 32 shots.  Batched: one fwi_gradient call for all
     shots (each launch covers every shot's tiles).  Plain: one call per shot."""
     import numpy as np
     import torch
 
     from paper_1912_08063_amd import api, workloads as wl
-    P = wl.c3(nt=nt, nshots=shots)
+    P = wl.shots_2d(nt=nt, nshots=shots)
     t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
     w, s, r = t(P.wavelet, torch.float32), t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
     cfg = api.Config(dt=P.dt, dx=P.dx, order=P.order, nsponge=P.nb, eta_max=P.eta_max,
@@ -97,8 +97,43 @@ def gradient_section(dev, nt, shots, every):
             "speedup": round(tp / tb, 3), "misfit": mis}
 
 
+def gradient3d_section(dev, nt, every):
+    """3-D gradient on the headline geometry (304^3 padded, 8th order) over nt
+    steps with every-k checkpoints: forward, recompute of each segment,
+    adjoint and imaging condition.  Reported against the forward alone."""
+    import numpy as np
+    import torch
+
+    from paper_1912_08063_amd import api, workloads as wl
+    P = wl.layered_3d(nt=nt)
+    t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
+    v, w = t(P.v, torch.float32), t(P.wavelet, torch.float32)
+    s, r = t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
+    cfg = api.Config(dt=P.dt, dx=P.dx, order=P.order, nsponge=P.nb, eta_max=P.eta_max,
+                     ckpt="every:%d" % every)
+    obs = api.forward(v, w, s, r, cfg)                              # untimed
+    v0 = 0.98 * v
+    ws, wf = api.Workspace(), api.Workspace()
+    api.gradient(v0, obs, w, s, r, cfg, workspace=ws)               # warm-up
+    api.forward(v0, w, s, r, cfg, workspace=wf)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mis, dv = api.gradient(v0, obs, w, s, r, cfg, workspace=ws)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    api.forward(v0, w, s, r, cfg, workspace=wf)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    log("3-D gradient: %.3f s (forward %.3f s)" % (tg, tf))
+    return {"workload": "3-D FWI gradient, 256^3 model + 24-cell sponge (304^3 padded), 8th "
+                        "order, %d steps, every-%d checkpoints" % (nt, every),
+            "gradient_s": round(tg, 4), "forward_s": round(tf, 4),
+            "gradient_over_forward": round(tg / tf, 3), "misfit": mis}
+
+
 def serve_section(nreq, scale, chunk):
-    """C4 (reduced grid/step scale): Poisson stream of mixed 2-D/3-D forward and
+    """Serving (reduced grid/step scale): Poisson stream of mixed 2-D/3-D forward and
     gradient requests at 0.8x the saturated rate; continuous batching vs one
     request at a time."""
     import numpy as np
@@ -135,10 +170,12 @@ def main():
     ap.add_argument("--nt", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="forward,gradient,serve",
-                    help="comma list of: forward (headline), gradient (C3), serve (C4)")
+    ap.add_argument("--sections", default="forward,gradient,gradient3d,serve",
+                    help="comma list of: forward (headline), gradient (2-D, 32 shots), "
+                         "gradient3d (headline geometry), serve (request stream)")
     ap.add_argument("--grad-nt", type=int, default=3000)
     ap.add_argument("--grad-shots", type=int, default=32)
+    ap.add_argument("--grad3d-nt", type=int, default=600)
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
@@ -175,7 +212,7 @@ def main():
               flush=True)
         return
     log("generating workload")
-    P = wl.c2(nt=args.nt)
+    P = wl.layered_3d(nt=args.nt)
     t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
     v, w = t(P.v, torch.float32), t(P.wavelet, torch.float32)
     s, r = t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
@@ -241,6 +278,8 @@ def main():
     sections = set(args.sections.split(","))
     if "gradient" in sections:
         out["gradient"] = gradient_section(dev, args.grad_nt, args.grad_shots, 50)
+    if "gradient3d" in sections:
+        out["gradient3d"] = gradient3d_section(dev, args.grad3d_nt, 50)
     if "serve" in sections:
         out["serving"] = serve_section(args.serve_requests, args.serve_scale, 50)
     if not args.no_cpu_baseline:

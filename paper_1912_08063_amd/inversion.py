@@ -105,7 +105,7 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=50)
     args = ap.parse_args(argv)
     log = lambda m: print("[fwi] " + m, file=sys.stderr, flush=True)
-    P = wl.c3(nt=args.nt, nshots=args.shots)
+    P = wl.shots_2d(nt=args.nt, nshots=args.shots)
     dev = torch.device("cuda:0")
     t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
     w, s, r = t(P.wavelet, torch.float32), t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)

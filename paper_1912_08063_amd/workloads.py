@@ -7,17 +7,18 @@ No public dataset is involved: every model is generated from a seed.
 Workloads (shapes and value distributions of the paper's setting, a 3-D
 acoustic medium sampled on a regular grid, Sections 3-4):
 
-* ``c1`` -- 2-D 128x128, dx 10 m, 2000 m/s plus a +300 m/s Gaussian anomaly
+* ``anomaly_2d`` -- 2-D 128x128, dx 10 m, 2000 m/s plus a +300 m/s Gaussian anomaly
   (sigma 8 cells) at the centre, dt 1 ms, 500 steps, 20-cell sponge, 15 Hz
   Ricker at (z 4, x 64), 128 receivers on row 4.
-* ``c2`` -- 3-D 256^3, dx 10 m, layered (8-12 layers, 1500-4500 m/s, 5 %
+* ``layered_3d`` -- 3-D 256^3, dx 10 m, layered (8-12 layers, 1500-4500 m/s, 5 %
   multiplicative noise), dt from CFL 0.4, 2000 steps, 24-cell sponge, 10 Hz
   Ricker at (4, 128, 128), 256x256 receivers on z 4.
-* ``c3`` -- 2-D 1024x320 (x by z), dx 12.5 m, smooth random truth in
+* ``shots_2d`` -- 2-D 1024x320 (x by z), dx 12.5 m, smooth random truth in
   1500-4500 m/s and a smoothed (sigma 20) start model, 32 shots, 3000 steps,
   8 Hz Ricker, 1024 receivers, every-50 checkpoints.
-* ``c4`` -- a Poisson stream of mixed 2-D / 3-D forward and gradient requests.
-* ``c5`` -- 3-D 512x512x256 (x, y, z), dx 10 m, layers plus an ellipsoidal
+* ``serve.make_stream`` -- a Poisson stream of mixed 2-D / 3-D forward and
+  gradient requests.
+* ``salt_3d`` -- 3-D 512x512x256 (x, y, z), dx 10 m, layers plus an ellipsoidal
   4500 m/s salt body, 3000 steps, revolve under a 40 GB wavefield budget,
   512x512 receivers; the oracle comparison runs on a 64^3 crop.
 """
@@ -163,34 +164,34 @@ def _pack(name, v, dx, dt, nt, order, nb, f, src_pos, rec_pos, eta_max=None, **k
                    int(order), int(nb), float(eta_max), w, src_pos, rec_pos, **kw)
 
 
-def c1(nt=500, order=8):
+def anomaly_2d(nt=500, order=8):
     v = gaussian_anomaly_2d()
     rec = surface_receivers(v.shape, 4)
-    return _pack("c1-2d-128x128-nt%d" % nt, v, 10.0, 1e-3, nt, order, 20, 15.0,
+    return _pack("anomaly-2d-128x128-nt%d" % nt, v, 10.0, 1e-3, nt, order, 20, 15.0,
                  [[4, 64]], rec)
 
 
-def c2(nt=2000, order=8, n=256, seed=2):
+def layered_3d(nt=2000, order=8, n=256, seed=2):
     rng = np.random.default_rng(seed)
     v = layered((n, n, n), rng)
     dt = dt_from_cfl(float(v.max()), 10.0, 0.4)
     rec = surface_receivers(v.shape, 4)
-    return _pack("c2-3d-%d^3-nt%d" % (n, nt), v, 10.0, dt, nt, order, 24, 10.0,
+    return _pack("layered-3d-%d^3-nt%d" % (n, nt), v, 10.0, dt, nt, order, 24, 10.0,
                  [[4, n // 2, n // 2]], rec)
 
 
-def c3(nt=3000, order=8, nshots=32, seed=3, nz=320, nx=1024):
+def shots_2d(nt=3000, order=8, nshots=32, seed=3, nz=320, nx=1024):
     rng = np.random.default_rng(seed)
     truth = smooth_random_2d(nz, nx, rng)
     start = smooth(truth, 20.0)
     spacing = nx // nshots
     src = [[4, spacing // 2 + spacing * i] for i in range(nshots)]
     rec = surface_receivers(truth.shape, 4)
-    return _pack("c3-2d-%dx%d-%dshots-nt%d" % (nx, nz, nshots, nt), truth, 12.5, 1e-3,
+    return _pack("shots-2d-%dx%d-%dshots-nt%d" % (nx, nz, nshots, nt), truth, 12.5, 1e-3,
                  nt, order, 20, 8.0, src, rec, v_start=start, ckpt="every:50")
 
 
-def c5(nt=3000, order=8, seed=5, shape=(256, 512, 512)):
+def salt_3d(nt=3000, order=8, seed=5, shape=(256, 512, 512)):
     rng = np.random.default_rng(seed)
     nz, ny, nx = shape
     centre = (160 * nz // 256, ny // 2, nx // 2)
@@ -198,19 +199,19 @@ def c5(nt=3000, order=8, seed=5, shape=(256, 512, 512)):
     v = salt_model(shape, rng, centre, semi)
     dt = dt_from_cfl(4500.0, 10.0, 0.4)
     rec = surface_receivers(v.shape, 4)
-    return _pack("c5-3d-%dx%dx%d-nt%d" % (nx, ny, nz, nt), v, 10.0, dt, nt, order, 24,
+    return _pack("salt-3d-%dx%dx%d-nt%d" % (nx, ny, nz, nt), v, 10.0, dt, nt, order, 24,
                  10.0, [[4, ny // 2, nx // 2]], rec, v_start=smooth(v, 8.0),
                  ckpt="revolve:40e9")
 
 
-def c5_crop(nt=3000, order=8, seed=5):
-    """64^3 crop of the c5 salt model straddling the salt top (z 80-143,
+def salt_3d_crop(nt=3000, order=8, seed=5):
+    """64^3 crop of the salt_3d model straddling the salt top (z 80-143,
     y/x 224-287), with its own sponge, centred source and 64x64 receivers."""
-    full = c5(nt=1, order=order, seed=seed)
+    full = salt_3d(nt=1, order=order, seed=seed)
     v = full.v[80:144, 224:288, 224:288].copy()
     rec = surface_receivers(v.shape, 4)
     dt = full.dt
-    return _pack("c5crop-3d-64^3-nt%d" % nt, v, 10.0, dt, nt, order, 24, 10.0,
+    return _pack("saltcrop-3d-64^3-nt%d" % nt, v, 10.0, dt, nt, order, 24, 10.0,
                  [[4, 32, 32]], rec, eta_max=default_eta_max(4500.0, 24, 10.0),
                  v_start=smooth(v, 4.0), ckpt="revolve:0")
 

@@ -43,7 +43,7 @@ def test_3d_many_tiles_thin_z():
 
 
 def test_c1_full():
-    g, o = _check(wl.c1())
+    g, o = _check(wl.anomaly_2d())
     assert np.abs(g).max() > 0
 
 

@@ -20,8 +20,8 @@ from paper_1912_08063_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 
 
-def test_c3_single_shot_gradient_full():
-    P = f32(wl.c3(nshots=32))
+def test_shots_2d_single_shot_gradient_full():
+    P = f32(wl.shots_2d(nshots=32))
     Q = wl.Problem(P.name, P.v, P.dx, P.dt, P.nt, P.order, P.nb, P.eta_max, P.wavelet[5:6],
                    P.src_pos[5:6], P.rec_pos[5:6])
     obs = np.asarray(oracle_forward(Q), np.float32).astype(np.float64)
@@ -32,8 +32,8 @@ def test_c3_single_shot_gradient_full():
     assert rel_l2(dv_g, dv_o) <= 1e-3, rel_l2(dv_g, dv_o)
 
 
-def test_c3_four_shot_batched_forward_full():
-    P = f32(wl.c3(nshots=32))
+def test_shots_2d_four_shot_batched_forward_full():
+    P = f32(wl.shots_2d(nshots=32))
     idx = [0, 11, 22, 31]
     Q = wl.Problem(P.name, P.v, P.dx, P.dt, P.nt, P.order, P.nb, P.eta_max, P.wavelet[idx],
                    P.src_pos[idx], P.rec_pos[idx])
@@ -43,17 +43,17 @@ def test_c3_four_shot_batched_forward_full():
         assert rel_l2(g[s], o[s]) <= 1e-4
 
 
-def test_c2_full_grid_first_100_steps():
-    P = f32(wl.c2(nt=100))
+def test_layered_3d_full_grid_first_100_steps():
+    P = f32(wl.layered_3d(nt=100))
     g = gpu_forward(P)
     o = oracle_forward(P)
     assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
 
 
-def test_c5_revolve_equals_every_k_full_size():
+def test_salt_3d_revolve_equals_every_k_full_size():
     import torch
     from paper_1912_08063_amd import api
-    P = f32(wl.c5())
+    P = f32(wl.salt_3d())
     vt, w, s, r = inputs(P)
     obs = api.forward(vt, w, s, r, cfg(P))
     v0 = dev(P.v_start, torch.float32)
@@ -68,8 +68,8 @@ def test_c5_revolve_equals_every_k_full_size():
     assert np.all(np.isfinite(a)) and np.abs(a).max() > 0
 
 
-def test_c5_crop_gradient_vs_oracle():
-    P = f32(wl.c5_crop(nt=600))
+def test_salt_3d_crop_gradient_vs_oracle():
+    P = f32(wl.salt_3d_crop(nt=600))
     obs = np.asarray(oracle_forward(P), np.float32).astype(np.float64)
     v0 = np.asarray(P.v_start, np.float32).astype(np.float64)
     mis_g, dv_g, _ = gpu_gradient(P, v0, obs, "revolve:6")
