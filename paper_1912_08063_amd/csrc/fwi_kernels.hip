@@ -173,11 +173,6 @@ __device__ __forceinline__ gfloat *plane_ptr(gfloat *f, int zmem, int64_t plane)
     return f + (int64_t)zmem * plane;
 }
 
-#ifndef FWI_ADJ_HALO_RING
-#define FWI_ADJ_HALO_RING 0
-#endif
-constexpr int kAdjHaloRing = FWI_ADJ_HALO_RING;   // bit 0: y halos, bit 1: x halos
-
 // --------------------------------------------------------------- 3-D step
 // One block: 4 wavefronts, a 64 (x) x 16 (y) tile, marching a chunk of z.
 // Per plane z: the LDS buffer (z & 1) holds plane z of the propagated field
@@ -195,14 +190,10 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     constexpr int LX = TX + 2 * M, LY = TY + 2 * M, Q = 2 * M + 1, LS = LY * LX;
     constexpr int NYH = (2 * M * TX + NT - 1) / NT;   // y-halo cells per thread
     constexpr int NXH = (TY * 2 * M + NT - 1) / NT;   // x-halo cells per thread
-    // halos travel with the queue front (loaded at plane z+M, the same
-    // iteration in which the neighbouring tiles load those rows as their own
-    // front, so the second read is an L2 hit) and wait in a register ring;
-    // the adjoint keeps one ring per field when kAdjHaloRing is set
-    constexpr bool HQY = !ADJ || ((kAdjHaloRing & 1) && M <= 4);   // rows above/below
-    constexpr bool HQX = !ADJ || ((kAdjHaloRing & 2) && M <= 4);   // columns left/right
-    constexpr bool HQ = HQY || HQX;
-    constexpr bool FQY = ADJ && HQY, FQX = ADJ && HQX, FQ = FQY || FQX;
+    // forward: halos travel with the queue front (loaded at plane z+M, the
+    // same iteration in which the neighbouring tiles load those rows as their
+    // own front, so the second read is an L2 hit) and wait in a register ring
+    constexpr bool HQ = !ADJ;
     constexpr Weights<M> W{};
     __shared__ float sp[2 * LS];
     __shared__ float sf[ADJ ? 2 * LS : 1];
@@ -312,32 +303,16 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     // ---- prologue: queue slots 0..2M hold planes z0-M .. z0+M; plane z0 in LDS
     float q[RY][Q];
     float f[ADJ ? RY : 1][ADJ ? Q : 1];
-    float hy[HQY ? NYH : 1][HQY ? Q : 1], hx[HQX ? NXH : 1][HQX ? Q : 1];
-    float fy[FQY ? NYH : 1][FQY ? Q : 1], fx[FQX ? NXH : 1][FQX ? Q : 1];
+    float hy[HQ ? NYH : 1][HQ ? Q : 1], hx[HQ ? NXH : 1][HQ ? Q : 1];
     if constexpr (HQ) {
         // halo ring: slot s holds the halos of plane z0 - M + s (s = M+1 .. 2M now)
 #pragma unroll
         for (int s = M + 1; s < Q; ++s) {
             const rsrc_t ph = plane_rsrc(cur, z0 + s, plane, pbytes);
-            if constexpr (HQY) {
 #pragma unroll
-                for (int h = 0; h < NYH; ++h) hy[h][s] = ldb(ph, hyo[h]);
-            }
-            if constexpr (HQX) {
+            for (int h = 0; h < NYH; ++h) hy[h][s] = ldb(ph, hyo[h]);
 #pragma unroll
-                for (int h = 0; h < NXH; ++h) hx[h][s] = ldb(ph, hxo[h]);
-            }
-            if constexpr (FQ) {
-                const rsrc_t fh = plane_rsrc(fwd, z0 + s, plane, pbytes);
-                if constexpr (FQY) {
-#pragma unroll
-                    for (int h = 0; h < NYH; ++h) fy[h][s] = ldb(fh, hyo[h]);
-                }
-                if constexpr (FQX) {
-#pragma unroll
-                    for (int h = 0; h < NXH; ++h) fx[h][s] = ldb(fh, hxo[h]);
-                }
-            }
+            for (int h = 0; h < NXH; ++h) hx[h][s] = ldb(ph, hxo[h]);
         }
     }
 #pragma unroll
@@ -406,13 +381,12 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                 }
                 const rsrc_t phq = HQ ? plane_rsrc(cur, z + 1 + 2 * M, plane, pbytes) : ph;
 #pragma unroll
-                for (int h = 0; h < NYH; ++h) nhy[h] = ldb(HQY ? phq : ph, hyo[h]);
+                for (int h = 0; h < NYH; ++h) nhy[h] = ldb(phq, hyo[h]);
 #pragma unroll
-                for (int h = 0; h < NXH; ++h) nhx[h] = ldb(HQX ? phq : ph, hxo[h]);
+                for (int h = 0; h < NXH; ++h) nhx[h] = ldb(phq, hxo[h]);
                 if constexpr (ADJ) {
                     const rsrc_t fq = plane_rsrc(fwd, z + 1 + 2 * M, plane, pbytes);
                     const rsrc_t fh = plane_rsrc(fwd, z + 1 + M, plane, pbytes);
-                    const rsrc_t fhq = FQ ? plane_rsrc(fwd, z + 1 + 2 * M, plane, pbytes) : fh;
                     const rsrc_t pg = plane_rsrc(grad, z + 1 + M, plane, pbytes);
 #pragma unroll
                     for (int i = 0; i < RY; ++i) {
@@ -420,9 +394,9 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                         ng[i] = accum ? ldb_stream(pg, roff[i]) : 0.f;
                     }
 #pragma unroll
-                    for (int h = 0; h < NYH; ++h) nfy[h] = ldb(FQY ? fhq : fh, hyo[h]);
+                    for (int h = 0; h < NYH; ++h) nfy[h] = ldb(fh, hyo[h]);
 #pragma unroll
-                    for (int h = 0; h < NXH; ++h) nfx[h] = ldb(FQX ? fhq : fh, hxo[h]);
+                    for (int h = 0; h < NXH; ++h) nfx[h] = ldb(fh, hxo[h]);
                 }
             }
             // ---- plane z
@@ -491,34 +465,24 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
 #pragma unroll
                 for (int h = 0; h < NYH; ++h)
                     if (hyl[h] >= 0) {
-                        if constexpr (HQY) {
+                        if constexpr (HQ) {
                             Ln[hyl[h]] = hy[h][(k + M + 1) % Q];
                             hy[h][k] = nhy[h];
                         } else {
                             Ln[hyl[h]] = nhy[h];
                         }
-                        if constexpr (FQY) {
-                            LFn[hyl[h]] = fy[h][(k + M + 1) % Q];
-                            fy[h][k] = nfy[h];
-                        } else if constexpr (ADJ) {
-                            LFn[hyl[h]] = nfy[h];
-                        }
+                        if constexpr (ADJ) LFn[hyl[h]] = nfy[h];
                     }
 #pragma unroll
                 for (int h = 0; h < NXH; ++h)
                     if (hxl[h] >= 0) {
-                        if constexpr (HQX) {
+                        if constexpr (HQ) {
                             Ln[hxl[h]] = hx[h][(k + M + 1) % Q];
                             hx[h][k] = nhx[h];
                         } else {
                             Ln[hxl[h]] = nhx[h];
                         }
-                        if constexpr (FQX) {
-                            LFn[hxl[h]] = fx[h][(k + M + 1) % Q];
-                            fx[h][k] = nfx[h];
-                        } else if constexpr (ADJ) {
-                            LFn[hxl[h]] = nfx[h];
-                        }
+                        if constexpr (ADJ) LFn[hxl[h]] = nfx[h];
                     }
             }
             __syncthreads();
@@ -936,7 +900,6 @@ static void launch_step_m(int ndim, int nw, bool adj, const Job *jobs, const int
         switch (nw) {   // wavefronts per block x rows per thread
         case 8: launch_3d<M, 8, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, st); break;
         case 42: launch_3d<M, 4, 2>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, st); break;
-        case 82: launch_3d<M, 8, 2>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, st); break;
         default: launch_3d<M, 4, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, st); break;
         }
     } else {
@@ -959,9 +922,6 @@ static int occupancy_m(int ndim, int nw, bool adj)
         if (nw == 8)
             e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, true, 8, 4>, 512, 0)
                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, false, 8, 4>, 512, 0);
-        else if (nw == 82)
-            e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, true, 8, 2>, 512, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, false, 8, 2>, 512, 0);
         else if (nw == 42)
             e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, true, 4, 2>, 256, 0)
                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, false, 4, 2>, 256, 0);

@@ -274,12 +274,12 @@ int shape_code(bool adj, int M)
 {
     if (const char *e = getenv(adj ? "FWI_WAVES_ADJ" : "FWI_WAVES")) {
         const int v = atoi(e);
-        if (v == 4 || v == 8 || v == 42 || v == 82) return v;
+        if (v == 4 || v == 8 || v == 42) return v;
     }
     return adj || M >= 8 ? 42 : 4;
 }
-int block_waves(int code) { return code == 8 || code == 82 ? 8 : 4; }
-int block_rows(int code) { return code == 42 || code == 82 ? 2 : 4; }
+int block_waves(int code) { return code == 8 ? 8 : 4; }
+int block_rows(int code) { return code == 42 ? 2 : 4; }
 
 void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *nzc, int *zc)
 {
