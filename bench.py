@@ -60,7 +60,40 @@ def cpu_baseline(P, nt_sample):
                       "(%.1f s, set-up included)" % (nt_sample, P.nt, secs)}
 
 
-def gradient_section(dev, nt, shots, every):
+def forward16_section(dev, nt):
+    """The headline geometry at 16th order (M = 8, a 49-point star): the
+    stencil step's rate and its HIP-event launch time."""
+    import numpy as np
+    import torch
+
+    from paper_1912_08063_amd import api, workloads as wl
+    P = wl.layered_3d(nt=nt, order=16)
+    t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
+    v, w = t(P.v, torch.float32), t(P.wavelet, torch.float32)
+    s, r = t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
+    cfg = api.Config(dt=P.dt, dx=P.dx, order=P.order, nsponge=P.nb, eta_max=P.eta_max)
+    ws = api.Workspace()
+    api.forward(v, w, s, r, cfg, workspace=ws)                      # warm-up
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    api.forward(v, w, s, r, cfg, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    log("16th-order forward: %d steps in %.1f ms" % (nt, ms))
+    us = ms * 1e3 / nt
+    return {"workload": "3-D acoustic forward, 256^3 model + 24-cell sponge (304^3 padded), "
+                        "16th order, %d steps" % nt,
+            "Gcell_updates_per_s": round(P.padded_cells * nt / (ms * 1e-3) / 1e9, 3),
+            "avg_launch_us": round(us, 2),
+            "hbm_frac": round(BYTES_PER_UPDATE * P.padded_cells / (us * 1e-6) / 1e9
+                              / HBM_PEAK_GBS, 4)}
+
+
+def gradient_section(dev, nt, shots, every, plain=True):
     """2-D FWI gradient, 1024x320 model, 32 shots.  Batched: one fwi_gradient call for all
     shots (each launch covers every shot's tiles).  Plain: one call per shot."""
     import numpy as np
@@ -82,6 +115,11 @@ def gradient_section(dev, nt, shots, every):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     log("gradient batched: %d shots in %.3f s" % (shots, tb))
+    out = {"workload": "2-D FWI gradient, 1024x320 model + 20-cell sponge, %d shots, %d steps, "
+                       "1024 receivers, every-%d checkpoints" % (shots, nt, every),
+           "batched_shots_per_s": round(shots / tb, 3), "misfit": mis}
+    if not plain:
+        return out
     ws1 = api.Workspace()
     api.gradient(v0, obs[:1], w[:1], s[:1], r[:1], cfg, workspace=ws1)
     torch.cuda.synchronize()
@@ -91,10 +129,8 @@ def gradient_section(dev, nt, shots, every):
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     log("gradient plain: %d shots in %.3f s" % (shots, tp))
-    return {"workload": "2-D FWI gradient, 1024x320 model + 20-cell sponge, %d shots, %d steps, "
-                        "1024 receivers, every-%d checkpoints" % (shots, nt, every),
-            "batched_shots_per_s": round(shots / tb, 3), "plain_shots_per_s": round(shots / tp, 3),
-            "speedup": round(tp / tb, 3), "misfit": mis}
+    out.update(plain_shots_per_s=round(shots / tp, 3), speedup=round(tp / tb, 3))
+    return out
 
 
 def gradient3d_section(dev, nt, every):
@@ -170,12 +206,16 @@ def main():
     ap.add_argument("--nt", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="forward,gradient,gradient3d,serve",
-                    help="comma list of: forward (headline), gradient (2-D, 32 shots), "
-                         "gradient3d (headline geometry), serve (request stream)")
+    ap.add_argument("--sections", default="forward,forward16,gradient,gradient3d,serve",
+                    help="comma list of: forward (headline), forward16 (16th order), gradient "
+                         "(2-D, 32 shots), gradient3d (headline geometry), serve (request "
+                         "stream)")
     ap.add_argument("--grad-nt", type=int, default=3000)
     ap.add_argument("--grad-shots", type=int, default=32)
     ap.add_argument("--grad3d-nt", type=int, default=600)
+    ap.add_argument("--no-grad-plain", action="store_true",
+                    help="gradient section: time only the batched call")
+    ap.add_argument("--fwd16-nt", type=int, default=500)
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
@@ -277,7 +317,10 @@ def main():
     }
     sections = set(args.sections.split(","))
     if "gradient" in sections:
-        out["gradient"] = gradient_section(dev, args.grad_nt, args.grad_shots, 50)
+        out["gradient"] = gradient_section(dev, args.grad_nt, args.grad_shots, 50,
+                                           plain=not args.no_grad_plain)
+    if "forward16" in sections:
+        out["forward16"] = forward16_section(dev, args.fwd16_nt)
     if "gradient3d" in sections:
         out["gradient3d"] = gradient3d_section(dev, args.grad3d_nt, 50)
     if "serve" in sections:

@@ -292,8 +292,10 @@ void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *
     // 3-D: as many z chunks as fill one wave of resident blocks of the forward
     // step kernel (its occupancy times the CU count): fewer leave the memory
     // system idle, more add z-chunk warm-up planes and a partial second wave.
-    // 2-D fields are small and cache-resident: many short chunks.
-    int64_t target = 8192;
+    // 2-D fields are small and largely cache-resident: many short chunks
+    // (16384 blocks: 12-row chunks for 32 shots of 1064 x 360, 8 % faster
+    // than 8192 on the 2-D gradient).
+    int64_t target = 16384;
     if (g.ndim == 3) {
         static int cus = 0;
         if (cus == 0) {
