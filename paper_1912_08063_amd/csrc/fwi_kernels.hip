@@ -117,8 +117,10 @@ __device__ __forceinline__ float leapfrog(float val, float prev, int d2, float e
 
 // Streams read or written once per launch (kappa', the previous level, the
 // new level, the gradient accumulator) are non-temporal, leaving L2 to the
-// rows that neighbouring tiles share (+4 % on the 3-D forward step).
-// FWI_STREAM_CACHED at build time restores ordinary accesses.
+// rows that neighbouring tiles share (+4 % on the 3-D forward step; keeping
+// kappa' or the new level cached instead, for reuse by the next step from the
+// Infinity Cache, measured no faster).  FWI_STREAM_CACHED at build time
+// restores ordinary accesses.
 // Field pointers come from the job table, so the compiler cannot see that
 // they address global memory; without the cast every access would be a
 // flat load (64-bit address arithmetic per access, and flat loads also hold
@@ -128,23 +130,6 @@ typedef GMEM float gfloat;
 
 __device__ __forceinline__ const gfloat *gptr(const float *p) { return (const gfloat *)p; }
 __device__ __forceinline__ gfloat *gptr(float *p) { return (gfloat *)p; }
-
-__device__ __forceinline__ float ld_stream(const gfloat *p)
-{
-#ifdef FWI_STREAM_CACHED
-    return *p;
-#else
-    return __builtin_nontemporal_load(p);
-#endif
-}
-__device__ __forceinline__ void st_stream(gfloat *p, float v)
-{
-#ifdef FWI_STREAM_CACHED
-    *p = v;
-#else
-    __builtin_nontemporal_store(v, p);
-#endif
-}
 
 // Plane accesses go through a buffer resource (base and size of one plane in
 // scalar registers) and a 32-bit per-lane byte offset: no per-lane address
