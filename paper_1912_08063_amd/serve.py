@@ -5,9 +5,12 @@ Requests -- forward modelling, or misfit and gradient, of one shot on its own
 slot is free and its HBM footprint (the job memory of fwi_job_bytes plus its
 inputs and outputs) fits the free budget; its velocity model and wavefield
 state then stay resident on the device until it finishes.  Every chunk of K
-time steps, all admitted jobs advance together through fwi_jobs_advance,
+time steps, the scheduled jobs advance together through fwi_jobs_advance,
 whose launches each cover the tiles of every job; requests that arrived in
-the meantime join at the next chunk boundary and finished ones leave.
+the meantime join at the next chunk boundary and finished ones leave.  By
+default each chunk runs the resident jobs with the least remaining work that
+fit the fill limit (preemptive shortest-remaining-work first); long jobs
+pause, resident, while short ones pass.
 
 The plain baseline is the same loop with one slot: one request at a time,
 each with launches of its own.
@@ -47,6 +50,8 @@ class Result:
     traces: Optional[np.ndarray] = None
     dv: Optional[np.ndarray] = None
     misfit: Optional[float] = None
+    seq: int = -1                  # completion index within the run
+    work: int = 0                  # padded cells x program operations, at admission
 
     @property
     def latency(self):
@@ -120,15 +125,32 @@ class _Active:
     pass
 
 
+POLICIES = ("srpt", "fifo")
+
+
 class Server:
-    """Admission by HBM footprint, resident job state, continuous batching."""
+    """Admission by HBM footprint, resident job state, continuous batching.
+
+    policy "srpt": every arrived request that fits the memory budget is
+    admitted and stays resident; each chunk advances the resident jobs with
+    the least remaining work (padded cells x program operations left) while
+    their cells stay within fill_cells, so a long job yields the GPU to short
+    ones that arrive during it and resumes afterwards.
+    policy "fifo": requests are admitted in arrival order while their cells
+    fit fill_cells, and every admitted job advances each chunk.
+    On the full-size request stream at 0.8x the saturated rate, srpt cuts the
+    median latency about 7x against fifo and one-at-a-time serving, and
+    raises p99, which the largest 3-D gradient jobs set, by about a quarter."""
 
     def __init__(self, device="cuda", hbm_budget=None, max_active=64, chunk=50,
-                 keep_outputs=False, fill_cells=24_000_000):
+                 keep_outputs=False, fill_cells=24_000_000, policy="srpt"):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         if hbm_budget is None:
+            # blocks that torch's caching allocator holds from earlier work
+            # are free for jobs: hand them back before measuring
+            torch.cuda.empty_cache()
             free, _ = torch.cuda.mem_get_info(self.device)
             hbm_budget = int(0.8 * free)
         self.budget = int(hbm_budget)
@@ -139,6 +161,9 @@ class Server:
         # what saturates the GPU: small jobs batch, a big job runs (nearly)
         # alone instead of slowing every other job down
         self.fill_cells = fill_cells
+        if policy not in POLICIES:
+            raise ValueError("policy must be one of %s" % (POLICIES,))
+        self.policy = policy
         self.ws = None
 
     # ---------------------------------------------------------------- sizes
@@ -191,12 +216,13 @@ class Server:
             a.r.data_ptr() if P.nrec else None, a.obs.data_ptr() if grad and P.nrec else None,
             a.traces.data_ptr() if P.nrec else None, a.dv.data_ptr() if grad else None,
             a.mem.data_ptr(), a.mem.numel(), stream)
+        a.work = P.padded_cells * _lib.fwi_job_query(a.handle)[1]
         return a
 
     def _finish(self, a, now):
         from . import _lib
         torch = self.torch
-        res = Result(a.req.rid, a.req.kind, a.req.arrival, a.admitted, now)
+        res = Result(a.req.rid, a.req.kind, a.req.arrival, a.admitted, now, work=a.work)
         if a.req.kind == "gradient":
             res.misfit = _lib.fwi_job_misfit(a.handle, torch.cuda.current_stream(
                 self.device).cuda_stream)
@@ -206,6 +232,24 @@ class Server:
                 res.dv = a.dv.cpu().numpy()
         _lib.fwi_job_destroy(a.handle)
         return res
+
+    def _select(self, active):
+        """The jobs that advance this chunk (see the class docstring)."""
+        from . import _lib
+        if self.policy == "fifo" or not self.fill_cells:
+            return active
+
+        def work(a):
+            _, left = _lib.fwi_job_query(a.handle)
+            return (a.req.problem.padded_cells * left, a.req.arrival, a.req.rid)
+        chosen, cells = [], 0
+        for a in sorted(active, key=work):
+            c = a.req.problem.padded_cells
+            if chosen and cells + c > self.fill_cells:
+                continue
+            chosen.append(a)
+            cells += c
+        return chosen
 
     # ------------------------------------------------------------------- loop
     def run(self, requests: List[Request], realtime=True, log=None):
@@ -237,7 +281,8 @@ class Server:
                 need = self.footprint(r)
                 if used + need > self.budget and active:
                     break
-                if self.fill_cells and active and cells + r.problem.padded_cells > self.fill_cells:
+                if (self.policy == "fifo" and self.fill_cells and active
+                        and cells + r.problem.padded_cells > self.fill_cells):
                     break
                 if need > self.budget:
                     raise MemoryError("request %d needs %d bytes > budget %d" %
@@ -253,8 +298,8 @@ class Server:
                 elif pending:
                     virtual = max(virtual, pending[0].arrival)
                 continue
-            _lib.fwi_jobs_advance([a.handle for a in active], self.chunk, self.ws.data_ptr(),
-                                  ws_bytes, stream)
+            _lib.fwi_jobs_advance([a.handle for a in self._select(active)], self.chunk,
+                                  self.ws.data_ptr(), ws_bytes, stream)
             torch.cuda.synchronize(self.device)
             chunks += 1
             now = clock() if realtime else virtual
@@ -263,6 +308,7 @@ class Server:
                 done, _ = _lib.fwi_job_query(a.handle)
                 if done:
                     results.append(self._finish(a, now))
+                    results[-1].seq = len(results) - 1
                     used -= a.footprint
                     cells -= a.req.problem.padded_cells
                     if log and len(results) % 10 == 0:
@@ -275,7 +321,7 @@ class Server:
         lat = np.array([r.latency for r in results])
         report = {
             "requests": len(results), "chunks": chunks, "chunk_steps": self.chunk,
-            "max_active": self.max_active, "fill_cells": self.fill_cells,
+            "max_active": self.max_active, "fill_cells": self.fill_cells, "policy": self.policy,
             "makespan_s": makespan,
             "shots_per_s": len(results) / makespan if makespan > 0 else None,
             "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
@@ -296,6 +342,10 @@ def main(argv=None):
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--policy", choices=list(POLICIES), default="srpt",
+                    help="batched server's scheduling (the plain server runs one job at a time)")
+    ap.add_argument("--compare", default="",
+                    help="comma list of other batched policies to serve the same stream with")
     args = ap.parse_args(argv)
     log = lambda m: print("[serve] " + m, file=sys.stderr, flush=True)
     reqs = []
@@ -314,17 +364,24 @@ def main(argv=None):
         # saturated throughput: everything arrives at t = 0
         for r in reqs:
             r.arrival = 0.0
-        _, sat = Server(max_active=args.max_active, chunk=args.chunk).run(reqs, realtime=True,
-                                                                        log=log)
+        _, sat = Server(max_active=args.max_active, chunk=args.chunk,
+                        policy=args.policy).run(reqs, realtime=True, log=log)
         out["saturated"] = sat
         rate = 0.8 * sat["shots_per_s"]
         log("saturated: %.2f shots/s" % sat["shots_per_s"])
     arr = np.cumsum(np.random.default_rng(args.seed).exponential(1.0 / rate, len(reqs)))
     for r, t in zip(reqs, arr):
         r.arrival = float(t)
-    _, rep = Server(max_active=args.max_active, chunk=args.chunk).run(reqs, realtime=True, log=log)
+    _, rep = Server(max_active=args.max_active, chunk=args.chunk,
+                    policy=args.policy).run(reqs, realtime=True, log=log)
     out["batched"] = dict(rep, rate=rate)
     log("batched: p50 %.3f s p99 %.3f s" % (rep["p50_latency_s"], rep["p99_latency_s"]))
+    for pol in [p for p in args.compare.split(",") if p and p != args.policy]:
+        _, repo = Server(max_active=args.max_active, chunk=args.chunk,
+                         policy=pol).run(reqs, realtime=True, log=log)
+        out["batched_" + pol] = dict(repo, rate=rate)
+        log("batched %s: p50 %.3f s p99 %.3f s" % (pol, repo["p50_latency_s"],
+                                                    repo["p99_latency_s"]))
     if not args.skip_plain:
         _, rep1 = Server(max_active=1, chunk=args.chunk).run(reqs, realtime=True, log=log)
         out["plain"] = dict(rep1, rate=rate)

@@ -94,3 +94,23 @@ def test_admission_respects_budget():
     srv.budget = biggest + 1   # at most one large job at a time
     results, rep = srv.run(reqs, realtime=False)
     assert rep["requests"] == 6
+
+
+def test_srpt_pauses_long_jobs_without_changing_results():
+    """A fill limit of one cell lets one job advance per chunk: the one with the
+    least remaining work.  Jobs then finish in order of their work, and every
+    result is bitwise that of the FIFO server, which advances all jobs at once."""
+    from paper_1912_08063_amd import serve
+    reqs = _stream(6, 0.06, seed=41)
+    srpt, rep = serve.Server(max_active=6, chunk=10, keep_outputs=True, fill_cells=1).run(
+        reqs, realtime=False)
+    fifo, _ = serve.Server(max_active=6, chunk=10, keep_outputs=True, policy="fifo",
+                           fill_cells=10 ** 12).run(reqs, realtime=False)
+    assert rep["requests"] == 6 and rep["policy"] == "srpt"
+    order = [r.rid for r in sorted(srpt, key=lambda r: r.seq)]
+    by_work = [r.rid for r in sorted(srpt, key=lambda r: (r.work, r.arrival, r.rid))]
+    assert order == by_work
+    for a, b in zip(srpt, fifo):
+        assert np.array_equal(a.traces, b.traces)
+        if a.kind == "gradient":
+            assert np.array_equal(a.dv, b.dv) and a.misfit == b.misfit
