@@ -1,9 +1,11 @@
 """Parity at the workloads' full sizes, in the launch configuration bench.py uses.
 
-* 2-D gradient workload (1024x320, 3000 steps): one shot's misfit and dv, and
-  a four-shot batched forward, element by element against the FP64 oracle.
+* 2-D gradient workload (1024x320, 3000 steps): one shot's misfit and dv, a
+  four-shot batched forward, and the whole 32-shot batched gradient that
+  bench.py times (marked slow), element by element against the FP64 oracle.
 * 3-D forward workload (256^3 + sponge): the full grid and receiver plane
-  against the oracle over the first 100 steps (the oracle needs ~1 min).
+  against the oracle over the first 100 steps, and the whole 2000-step run
+  that bench.py times (marked slow: about two minutes of the oracle).
 * 3-D revolve workload (512x512x256, 3000 steps, 40 GB snapshot budget): the
   revolve gradient equals the every-50 gradient bitwise at full size (a
   property that holds at any size: both recompute the same forward levels),
@@ -32,6 +34,20 @@ def test_shots_2d_single_shot_gradient_full():
     assert rel_l2(dv_g, dv_o) <= 1e-3, rel_l2(dv_g, dv_o)
 
 
+@pytest.mark.slow
+def test_shots_2d_all_shots_batched_gradient_full():
+    """The benchmarked gradient call itself: 32 shots in shared launches, 3000
+    steps, every-50 checkpoints; misfit and dv summed over the shots against
+    the oracle's (about two minutes of the oracle)."""
+    P = f32(wl.shots_2d(nshots=32))
+    obs = np.asarray(oracle_forward(P), np.float32).astype(np.float64)
+    v0 = np.asarray(P.v_start, np.float32).astype(np.float64)
+    mis_g, dv_g, _ = gpu_gradient(P, v0, obs, "every:50")
+    mis_o, dv_o = oracle_gradient(P, v0, obs)
+    assert abs(mis_g - mis_o) <= 1e-3 * mis_o
+    assert rel_l2(dv_g, dv_o) <= 1e-3, rel_l2(dv_g, dv_o)
+
+
 def test_shots_2d_four_shot_batched_forward_full():
     P = f32(wl.shots_2d(nshots=32))
     idx = [0, 11, 22, 31]
@@ -45,6 +61,17 @@ def test_shots_2d_four_shot_batched_forward_full():
 
 def test_layered_3d_full_grid_first_100_steps():
     P = f32(wl.layered_3d(nt=100))
+    g = gpu_forward(P)
+    o = oracle_forward(P)
+    assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
+
+
+@pytest.mark.slow
+def test_layered_3d_headline_run_full_length():
+    """The benchmarked run itself: 256^3 model + 24-cell sponge, 8th order, all
+    2000 steps, every trace of the 256 x 256 receiver grid against the oracle
+    (about two minutes of the oracle on 16 host threads)."""
+    P = f32(wl.layered_3d(nt=2000))
     g = gpu_forward(P)
     o = oracle_forward(P)
     assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
