@@ -93,6 +93,48 @@ def forward16_section(dev, nt):
                               / HBM_PEAK_GBS, 4)}
 
 
+def cpu_gradient_2d(nt):
+    """The oracle's misfit + gradient for one shot of the 2-D gradient workload,
+    full length, beside the GPU's batched shots/s."""
+    import numpy as np
+
+    import oracle
+    from paper_1912_08063_amd import workloads as wl
+    P = wl.shots_2d(nt=nt, nshots=32)
+    obs = np.zeros((1, P.nt, P.nrec))
+    t0 = time.perf_counter()
+    oracle.gradient(P.v_start, P.wavelet[:1], P.src_pos[:1], P.rec_pos[:1], obs, P.dx, P.dt,
+                    P.order, P.nb, P.eta_max)
+    secs = time.perf_counter() - t0
+    return {"value": round(1.0 / secs, 4), "unit": "shots/s", "kind": "oracle",
+            "sample": "fp64 oracle gradient (forward with stored states, adjoint, imaging "
+                      "condition) of one of the 32 shots, all %d steps (%.1f s)" % (nt, secs)}
+
+
+def cpu_gradient_3d(nt_sample, nt):
+    """The oracle's gradient on the 3-D headline grid over two bounded step
+    counts (its stored states grow with nt): set-up plus a per-step cost from
+    their difference, extrapolated to the GPU section's nt."""
+    import numpy as np
+
+    import oracle
+    from paper_1912_08063_amd import workloads as wl
+    secs = []
+    for n in (nt_sample // 2, nt_sample):
+        P = wl.layered_3d(nt=n)
+        obs = np.zeros((1, P.nt, P.nrec))
+        t0 = time.perf_counter()
+        oracle.gradient(0.98 * P.v, P.wavelet, P.src_pos, P.rec_pos, obs, P.dx, P.dt,
+                        P.order, P.nb, P.eta_max)
+        secs.append(time.perf_counter() - t0)
+    per_step = (secs[1] - secs[0]) / (nt_sample - nt_sample // 2)
+    total = secs[1] + (nt - nt_sample) * per_step
+    return {"value": round(total, 1), "unit": "s per %d-step gradient" % nt, "kind": "oracle",
+            "sample": "fp64 oracle gradient on the 304^3 padded grid at %d and %d steps "
+                      "(%.1f s, %.1f s), extrapolated with the per-step difference to %d steps"
+                      % (nt_sample // 2, nt_sample, secs[0], secs[1], nt)}
+
+
 def gradient_section(dev, nt, shots, every, plain=True):
     """2-D FWI gradient, 1024x320 model, 32 shots.  Batched: one fwi_gradient call for all
     shots (each launch covers every shot's tiles).  Plain: one call per shot."""
@@ -216,6 +258,7 @@ def main():
     ap.add_argument("--no-grad-plain", action="store_true",
                     help="gradient section: time only the batched call")
     ap.add_argument("--fwd16-nt", type=int, default=500)
+    ap.add_argument("--cpu-grad3d-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
@@ -328,6 +371,13 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %d steps)" % args.cpu_steps)
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps)
+        if "gradient" in sections:
+            log("cpu baseline: oracle 2-D gradient, one shot")
+            out["cpu_baseline"]["gradient"] = cpu_gradient_2d(args.grad_nt)
+        if "gradient3d" in sections:
+            log("cpu baseline: oracle 3-D gradient sample")
+            out["cpu_baseline"]["gradient3d"] = cpu_gradient_3d(args.cpu_grad3d_steps,
+                                                                 args.grad3d_nt)
     print(json.dumps(out), flush=True)
 
 
