@@ -57,6 +57,9 @@ def test_shots_2d_four_shot_batched_forward_full():
     o = oracle_forward(Q)
     for s in range(4):
         assert rel_l2(g[s], o[s]) <= 1e-4
+        # fp32 floor of the difference-form star over 3000 steps is ~5e-6; a
+        # plain-sum Laplacian (c_0 p + sum c_m (p_+m + p_-m)) sits near 5e-5
+        assert rel_l2(g[s], o[s]) <= 1.5e-5, rel_l2(g[s], o[s])
 
 
 def test_layered_3d_full_grid_first_100_steps():
