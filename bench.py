@@ -259,7 +259,7 @@ def main():
                     help="gradient section: time only the batched call")
     ap.add_argument("--fwd16-nt", type=int, default=500)
     ap.add_argument("--cpu-grad3d-steps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device copy of GIB GiB (counter calibration)")
