@@ -13,7 +13,8 @@
  *          order in Section 4); orders 2, 4, 8, 16 are accepted.
  *   Eq. 1  least-squares misfit phi = ||d_mod - d_obs||^2 (summed over shots),
  *          and its exact gradient with respect to the model velocity
- *          (Section 1: "misfit evaluation and computation of its gradient").
+ *          (Section 1 names the misfit and its gradient as the costly part of
+ *          every FWI iteration).
  *
  * Conventions shared by every entry point
  *   - All array pointers are DEVICE pointers owned by the caller, unless the

@@ -16,12 +16,12 @@ imaging on TPUs"):
 * Eq. 3 -- leapfrog update  P^{n+1} = -P^{n-1} + 2P^n + v^2 dt^2 lap P^n + dt^2 s^n,
   extended by a sponge (damping 2*eta*P_t, centred), which reduces to Eq. 3
   exactly where eta = 0 (the whole model grid).
-* Fig. 3 / Section 3 ("order >= 8") -- central 2M-th order star Laplacian;
-  Section 4 -- 8th and 16th order.
-* Section 1 ("misfit evaluation and computation of its gradient") -- the
-  gradient here is the exact gradient of the discrete misfit (discretise,
-  then differentiate), computed with the adjoint recurrence in the scaled
-  variable psi = kappa*alpha*lambda.
+* Fig. 3 / Section 3 (stencils of order 8 and above) -- central 2M-th order
+  star Laplacian; Section 4 -- 8th and 16th order.
+* Section 1 (the misfit and its gradient, the costly part of each FWI
+  iteration) -- the gradient here is the exact gradient of the discrete
+  misfit (discretise, then differentiate), computed with the adjoint
+  recurrence in the scaled variable psi = kappa*alpha*lambda.
 
 Readings of points the paper leaves open (source scaling dt^2 w / dx^D,
 trace n = field at time (n+1) dt, zero initial state, sponge outside the

@@ -4,7 +4,7 @@ Tolerance: relative L2 <= 1e-4 on traces (fp32 kernels against an fp64
 reference), per shot and overall.  Sizes span several tiles in every axis and
 ragged tails; edge cases cover empty receiver lists, no sponge, duplicated
 receivers, sources and receivers on the model corners, one time step, and
-every supported stencil order.
+every supported stencil order, and models smaller than the stencil radius.
 """
 import numpy as np
 import pytest
@@ -32,7 +32,7 @@ def test_small_2d_ragged(order):
     _check(wl.small_2d(nz=150, nx=203, nt=160, order=order, nshots=2, nrec=31))
 
 
-@pytest.mark.parametrize("order", [8, 16])
+@pytest.mark.parametrize("order", [8, 16, 4, 2])
 def test_small_3d_ragged(order):
     _check(wl.small_3d(shape=(45, 37, 150), nt=80, order=order, nshots=2, nrec=29))
 
@@ -42,7 +42,7 @@ def test_3d_many_tiles_thin_z():
     _check(wl.small_3d(shape=(6, 70, 200), nt=40, nb=3, nrec=40))
 
 
-def test_c1_full():
+def test_anomaly_2d_full():
     g, o = _check(wl.anomaly_2d())
     assert np.abs(g).max() > 0
 
@@ -56,6 +56,24 @@ def test_no_sponge_and_corners():
     P3.src_pos[0] = [11, 12, 69]
     P3.rec_pos[0] = [[0, 0, 0], [11, 0, 69]]
     _check(P3)
+
+
+def test_degenerate_grids():
+    """Models smaller than the stencil radius, one cell thick, with and without
+    a sponge: the frames and the clamped loads carry the whole computation."""
+    P = wl.small_2d(nz=1, nx=1, nt=30, nb=0, nrec=1)
+    P.src_pos[0] = [0, 0]
+    P.rec_pos[0] = [[0, 0]]
+    _check(P)
+    P = wl.small_2d(nz=2, nx=3, nt=30, nb=4, nrec=2)
+    P.src_pos[0] = [1, 2]
+    P.rec_pos[0] = [[0, 0], [1, 1]]
+    _check(P)
+    for nb in (0, 3):
+        P3 = wl.small_3d(shape=(1, 2, 3), nt=25, nb=nb, nrec=2)
+        P3.src_pos[0] = [0, 1, 2]
+        P3.rec_pos[0] = [[0, 0, 0], [0, 1, 1]]
+        _check(P3)
 
 
 def test_duplicate_receivers_and_single_step():
