@@ -82,7 +82,7 @@ def _lp(a):
 
 
 # --------------------------------------------------------------------------
-# Stencil weights (Fig. 3; "order >= 8", Section 3; 8th and 16th, Section 4)
+# Stencil weights (Fig. 3; order 8 or more, Section 3; 8th and 16th, Section 4)
 # --------------------------------------------------------------------------
 def fd_weights(order: int) -> list:
     """Exact central second-derivative weights c_0..c_M for spatial order 2M.
