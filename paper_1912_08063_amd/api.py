@@ -61,18 +61,48 @@ def parse_ckpt(spec: str) -> _lib.FwiCkpt:
     return c
 
 
-def _shots(v, src, src_pos, rec_pos):
+def _shots(v, src, src_pos, rec_pos, nt=None):
+    """Brings the inputs to the library's layout and checks every shape against
+    the problem: the C ABI takes no array lengths, so an array shorter than the
+    problem implies would be read or written out of bounds.
+
+    src [S][L] or [L] (one wavelet for every shot), src_pos [S][D] or [D],
+    rec_pos [S][R][D] or [R][D] (shared by every shot); nt <= L steps (default
+    L).  Returns src [S][nt], src_pos [S][D], rec_pos [S][R][D], contiguous."""
     D = v.dim()
     if D not in (2, 3):
         raise ValueError("v must be 2-D or 3-D")
-    src = src.reshape(-1, src.shape[-1]) if src.dim() == 1 else src
+    for name, t in (("src", src), ("src_pos", src_pos), ("rec_pos", rec_pos)):
+        if t.device != v.device:
+            raise ValueError("%s is on %s, v on %s" % (name, t.device, v.device))
+    if src_pos.dim() not in (1, 2) or src_pos.shape[-1] != D:
+        raise ValueError("src_pos must be [S][%d] or [%d], got %s" % (D, D, tuple(src_pos.shape)))
     src_pos = src_pos.reshape(-1, D)
     S = src_pos.shape[0]
-    if src.shape[0] == 1 and S > 1:
-        src = src.expand(S, src.shape[1])
-    if rec_pos.dim() == 2:
+    if S < 1:
+        raise ValueError("no shots")
+    if src.dim() == 1:
+        src = src.unsqueeze(0)
+    if src.dim() != 2 or src.shape[0] not in (1, S):
+        raise ValueError("src must be [S][nt] or [nt] with S = %d, got %s" % (S, tuple(src.shape)))
+    nt = src.shape[1] if nt is None else int(nt)
+    if not 1 <= nt <= src.shape[1]:
+        raise ValueError("nt = %d needs 1 <= nt <= %d (the wavelet length)" % (nt, src.shape[1]))
+    src = src[:, :nt].expand(S, nt)
+    if rec_pos.dim() == 2 and rec_pos.shape[-1] == D:
         rec_pos = rec_pos.unsqueeze(0).expand(S, rec_pos.shape[0], D)
+    if rec_pos.dim() != 3 or rec_pos.shape[0] != S or rec_pos.shape[2] != D:
+        raise ValueError("rec_pos must be [%d][R][%d] or [R][%d], got %s"
+                         % (S, D, D, tuple(rec_pos.shape)))
     return src.contiguous(), src_pos.contiguous(), rec_pos.contiguous()
+
+
+def _check_traces(t, name, S, nt, R, device):
+    """obs / out arrays: [S][nt][R] float32 on the model's device."""
+    if tuple(t.shape) != (S, nt, R):
+        raise ValueError("%s must be [%d][%d][%d], got %s" % (name, S, nt, R, tuple(t.shape)))
+    if t.device != device:
+        raise ValueError("%s is on %s, v on %s" % (name, t.device, device))
 
 
 def default_eta_max(vmax: float, nsponge: int, dx: float) -> float:
@@ -125,12 +155,15 @@ def forward(v, src, src_pos, rec_pos, cfg: Config, nt: Optional[int] = None,
     src = _require(src, "src", torch.float32)
     src_pos = _require(src_pos, "src_pos", torch.int32)
     rec_pos = _require(rec_pos, "rec_pos", torch.int32)
-    src, src_pos, rec_pos = _shots(v, src, src_pos, rec_pos)
-    S, R = src_pos.shape[0], rec_pos.shape[1]
-    nt = src.shape[1] if nt is None else int(nt)
+    src, src_pos, rec_pos = _shots(v, src, src_pos, rec_pos, nt)
+    S, R, nt = src_pos.shape[0], rec_pos.shape[1], src.shape[1]
     prob = make_problem(v, nt, cfg, S, R)
     nbytes = _lib.fwi_workspace_bytes(prob, _lib.MODE_FORWARD)
     ws = (workspace or Workspace()).get(nbytes, v.device)
+    if out is not None:
+        _check_traces(out, "out", S, nt, R, v.device)
+        if out.dtype != torch.float32 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor")
     traces = out if out is not None else torch.empty((S, nt, R), dtype=torch.float32,
                                                      device=v.device)
     _lib.fwi_forward(prob, v.data_ptr(), src.data_ptr(), src_pos.data_ptr(),
@@ -148,8 +181,8 @@ def gradient(v, obs, src, src_pos, rec_pos, cfg: Config, return_traces=False,
     src_pos = _require(src_pos, "src_pos", torch.int32)
     rec_pos = _require(rec_pos, "rec_pos", torch.int32)
     src, src_pos, rec_pos = _shots(v, src, src_pos, rec_pos)
-    S, R = src_pos.shape[0], rec_pos.shape[1]
-    nt = src.shape[1]
+    S, R, nt = src_pos.shape[0], rec_pos.shape[1], src.shape[1]
+    _check_traces(obs, "obs", S, nt, R, v.device)
     prob = make_problem(v, nt, cfg, S, R)
     ck = parse_ckpt(cfg.ckpt)
     nbytes = _lib.fwi_workspace_bytes(prob, _lib.MODE_GRADIENT, ck)
