@@ -189,6 +189,25 @@ class Server:
         return job + io + 4 * P.src_pos.size + 4 * P.rec_pos.size
 
     # -------------------------------------------------------------- admission
+    @staticmethod
+    def check_request(req: Request):
+        """The arrays of a one-shot request against its problem (the job API
+        reads them by the problem's sizes)."""
+        P = req.problem
+        D, nt = P.v.ndim, P.nt
+        if req.kind not in ("forward", "gradient"):
+            raise ValueError("request %d: kind must be forward or gradient" % req.rid)
+        if D not in (2, 3):
+            raise ValueError("request %d: the model must be 2-D or 3-D" % req.rid)
+        if np.shape(P.src_pos) != (1, D):
+            raise ValueError("request %d: src_pos must be [1][%d]" % (req.rid, D))
+        if np.ndim(P.rec_pos) != 3 or np.shape(P.rec_pos)[0] != 1 or np.shape(P.rec_pos)[2] != D:
+            raise ValueError("request %d: rec_pos must be [1][R][%d]" % (req.rid, D))
+        if np.shape(P.wavelet) != (1, nt):
+            raise ValueError("request %d: wavelet must be [1][%d]" % (req.rid, nt))
+        if req.kind == "gradient" and np.shape(req.obs) != (1, nt, P.nrec):
+            raise ValueError("request %d: obs must be [1][%d][%d]" % (req.rid, nt, P.nrec))
+
     def _admit(self, req: Request, now):
         from . import _lib
         torch = self.torch
@@ -261,6 +280,7 @@ class Server:
         for r in pending:
             if r.kind == "gradient" and r.obs is None:
                 raise ValueError("gradient request %d has no observed data" % r.rid)
+            self.check_request(r)
         active, results = [], []
         used = 0
         cells = 0

@@ -62,3 +62,21 @@ def test_trace_arrays():
     for shape in [(3, 40, 4), (3, 39, 5), (2, 40, 5), (40, 5)]:
         with pytest.raises(ValueError):
             _check_traces(torch.zeros(shape), "obs", 3, 40, 5, torch.device("cpu"))
+
+
+def test_serving_requests_checked():
+    import numpy as np
+
+    from paper_1912_08063_amd import serve, workloads as wl
+    P = wl.small_2d(nz=20, nx=30, nt=15, nrec=4)
+    serve.Server.check_request(serve.Request(0, "forward", 0.0, P))
+    g = serve.Request(1, "gradient", 0.0, P, obs=np.zeros((1, 15, 4), np.float32))
+    serve.Server.check_request(g)
+    for bad in (serve.Request(2, "gradient", 0.0, P, obs=np.zeros((1, 14, 4))),
+                serve.Request(3, "other", 0.0, P)):
+        with pytest.raises(ValueError):
+            serve.Server.check_request(bad)
+    Q = wl.small_2d(nz=20, nx=30, nt=15, nrec=4)
+    Q.wavelet = Q.wavelet[:, :10]
+    with pytest.raises(ValueError):
+        serve.Server.check_request(serve.Request(4, "forward", 0.0, Q))
