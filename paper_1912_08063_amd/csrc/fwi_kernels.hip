@@ -196,10 +196,14 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     constexpr int LX = TX + 2 * M, LY = TY + 2 * M, Q = 2 * M + 1, LS = LY * LX;
     constexpr int NYH = (2 * M * TX + NT - 1) / NT;   // y-halo cells per thread
     constexpr int NXH = (TY * 2 * M + NT - 1) / NT;   // x-halo cells per thread
-    // forward: halos travel with the queue front (loaded at plane z+M, the
-    // same iteration in which the neighbouring tiles load those rows as their
-    // own front, so the second read is an L2 hit) and wait in a register ring
-    constexpr bool HQ = !ADJ;
+    // forward up to 8th order: halos travel with the queue front (loaded at
+    // plane z+M, the same iteration in which the neighbouring tiles load those
+    // rows as their own front, so the second read is an L2 hit) and wait in a
+    // register ring.  At 16th order the ring would hold 5 x 17 values per
+    // thread; without it the step runs at 4 instead of 2 waves per SIMD and
+    // 46 % faster (122 vs 178 us on a 304^3 grid), while at 8th order the ring
+    // wins (89 vs 94 us).
+    constexpr bool HQ = !ADJ && M <= 4;
     constexpr Weights<M> W{};
     constexpr int KD = kDiffRadii < M ? kDiffRadii : M;   // radii in difference form
     __shared__ float sp[2 * LS];
