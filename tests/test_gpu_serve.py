@@ -114,3 +114,25 @@ def test_srpt_pauses_long_jobs_without_changing_results():
         assert np.array_equal(a.traces, b.traces)
         if a.kind == "gradient":
             assert np.array_equal(a.dv, b.dv) and a.misfit == b.misfit
+
+
+def test_mixed_orders_in_one_advance():
+    """8th- and 16th-order jobs, 2-D and 3-D, forward and gradient, advanced
+    together: each (dimension, order, phase) forms its own launch group, and
+    every result is bitwise that of the stand-alone call."""
+    from paper_1912_08063_amd import serve
+    probs = [("forward", wl.small_2d(nz=30, nx=90, nt=60, order=16, nrec=9, seed=3)),
+             ("gradient", wl.small_2d(nz=28, nx=75, nt=55, order=8, nrec=7, seed=4)),
+             ("gradient", wl.small_3d(shape=(14, 12, 70), nt=40, order=16, nrec=6, seed=5)),
+             ("forward", wl.small_3d(shape=(12, 15, 66), nt=45, order=8, nrec=8, seed=6))]
+    reqs = [serve.Request(i, kind, 0.0, f32(P)) for i, (kind, P) in enumerate(probs)]
+    serve.attach_observed(reqs)
+    chunk = 16
+    results, rep = serve.Server(max_active=4, chunk=chunk, keep_outputs=True,
+                                policy="fifo").run(reqs, realtime=False)
+    assert rep["requests"] == 4
+    for req, res in zip(reqs, results):
+        tr, dv, mis = _standalone(req, chunk)
+        assert np.array_equal(res.traces, tr), req.problem.name
+        if req.kind == "gradient":
+            assert np.array_equal(res.dv, dv) and res.misfit == mis
