@@ -175,7 +175,7 @@ def gradient_section(dev, nt, shots, every, plain=True):
     return out
 
 
-def gradient3d_section(dev, nt, every):
+def gradient3d_section(dev, nt, every, order=8):
     """3-D gradient on the headline geometry (304^3 padded, 8th order) over nt
     steps with every-k checkpoints: forward, recompute of each segment,
     adjoint and imaging condition.  Reported against the forward alone."""
@@ -183,7 +183,7 @@ def gradient3d_section(dev, nt, every):
     import torch
 
     from paper_1912_08063_amd import api, workloads as wl
-    P = wl.layered_3d(nt=nt)
+    P = wl.layered_3d(nt=nt, order=order)
     t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
     v, w = t(P.v, torch.float32), t(P.wavelet, torch.float32)
     s, r = t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
@@ -204,8 +204,8 @@ def gradient3d_section(dev, nt, every):
     torch.cuda.synchronize()
     tf = time.perf_counter() - t0
     log("3-D gradient: %.3f s (forward %.3f s)" % (tg, tf))
-    return {"workload": "3-D FWI gradient, 256^3 model + 24-cell sponge (304^3 padded), 8th "
-                        "order, %d steps, every-%d checkpoints" % (nt, every),
+    return {"workload": "3-D FWI gradient, 256^3 model + 24-cell sponge (304^3 padded), "
+                        "order %d, %d steps, every-%d checkpoints" % (order, nt, every),
             "gradient_s": round(tg, 4), "forward_s": round(tf, 4),
             "gradient_over_forward": round(tg / tf, 3), "misfit": mis}
 
@@ -255,6 +255,7 @@ def main():
     ap.add_argument("--grad-nt", type=int, default=3000)
     ap.add_argument("--grad-shots", type=int, default=32)
     ap.add_argument("--grad3d-nt", type=int, default=600)
+    ap.add_argument("--grad3d-order", type=int, default=8)
     ap.add_argument("--no-grad-plain", action="store_true",
                     help="gradient section: time only the batched call")
     ap.add_argument("--fwd16-nt", type=int, default=500)
@@ -351,7 +352,7 @@ def main():
                                               / (ms * 1e-3) / 1e9, 3),
         },
         "roofline": {
-            "bound": "hbm", "kernel": "k_step3d<4,false> (stencil step, one launch per time step)",
+            "bound": "hbm", "kernel": "k_step3d<4,0,4,4> (forward stencil step, one launch per time step)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(),
             "bytes_per_launch": bytes_per_launch,
@@ -365,7 +366,7 @@ def main():
     if "forward16" in sections:
         out["forward16"] = forward16_section(dev, args.fwd16_nt)
     if "gradient3d" in sections:
-        out["gradient3d"] = gradient3d_section(dev, args.grad3d_nt, 50)
+        out["gradient3d"] = gradient3d_section(dev, args.grad3d_nt, 50, args.grad3d_order)
     if "serve" in sections:
         out["serving"] = serve_section(args.serve_requests, args.serve_scale, 50)
     if not args.no_cpu_baseline:

@@ -187,7 +187,13 @@ __device__ __forceinline__ gfloat *plane_ptr(gfloat *f, int zmem, int64_t plane)
 // the previous level.  While plane z is computed, plane z+1 is already being
 // loaded (the next queue front, kappa', previous level, halos), and written
 // to the other LDS buffer afterwards: one barrier per plane.
-template <int M, bool ADJ, int NW, int RY>
+// Step modes: the forward step; the adjoint step with the imaging condition
+// fused in (two stencil fields); and the adjoint as two single-field passes,
+// the psi update alone and the imaging condition g += psi^{k+1} * L'p^k
+// alone, each with the forward step's memory pattern (see launch_3d).
+enum StepMode { kFwd = 0, kAdj = 1, kAdjPsi = 2, kImage = 3 };
+
+template <int M, int MODE, int NW, int RY>
 __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs,
                                                 const int *__restrict__ prefix, int njobs,
                                                 int step, int ttiles, int remap)
@@ -196,18 +202,21 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     constexpr int LX = TX + 2 * M, LY = TY + 2 * M, Q = 2 * M + 1, LS = LY * LX;
     constexpr int NYH = (2 * M * TX + NT - 1) / NT;   // y-halo cells per thread
     constexpr int NXH = (TY * 2 * M + NT - 1) / NT;   // x-halo cells per thread
-    // forward up to 8th order: halos travel with the queue front (loaded at
-    // plane z+M, the same iteration in which the neighbouring tiles load those
-    // rows as their own front, so the second read is an L2 hit) and wait in a
-    // register ring.  At 16th order the ring would hold 5 x 17 values per
-    // thread; without it the step runs at 4 instead of 2 waves per SIMD and
-    // 46 % faster (122 vs 178 us on a 304^3 grid), while at 8th order the ring
-    // wins (89 vs 94 us).
-    constexpr bool HQ = !ADJ && M <= 4;
+    constexpr bool ADJ = MODE != kFwd;     // adjoint time order and tiling
+    constexpr bool FUSED = MODE == kAdj;   // second stencil field (p^k) and g
+    constexpr bool IMG = MODE == kImage;
+    // single-field modes up to 8th order: halos travel with the queue front
+    // (loaded at plane z+M, the same iteration in which the neighbouring tiles
+    // load those rows as their own front, so the second read is an L2 hit)
+    // and wait in a register ring.  At 16th order the ring would hold 5 x 17
+    // values per thread; without it the step runs at 4 instead of 2 waves per
+    // SIMD and 46 % faster (122 vs 178 us on a 304^3 grid), while at 8th order
+    // the ring wins (89 vs 94 us).
+    constexpr bool HQ = !FUSED && M <= 4;
     constexpr Weights<M> W{};
     constexpr int KD = kDiffRadii < M ? kDiffRadii : M;   // radii in difference form
     __shared__ float sp[2 * LS];
-    __shared__ float sf[ADJ ? 2 * LS : 1];
+    __shared__ float sf[FUSED ? 2 * LS : 1];
 
     const int tid = threadIdx.x;
     int b = blockIdx.x;
@@ -235,24 +244,32 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     const int tz = local / T.nty;
     const int z0 = tz * T.zc, z1 = min(z0 + T.zc, nz);
 
-    const gfloat *cur, *prv;
+    // cur: the stencil field; prv and kap: the two pointwise streams; out.
+    // Imaging mode: cur = p^k, prv = psi^{k+1}, kap = out = g.
+    const gfloat *cur, *prv, *kap = gptr(J->kappa);
     gfloat *out;
     const gfloat *fwd = nullptr;
     gfloat *grad = nullptr;
-    bool accum = false;
-    if constexpr (ADJ) {
+    const bool accum = ADJ && J->accumulate && n <= J->nt - 1;
+    if constexpr (IMG) {
+        if (!accum) return;
+        cur = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
+        prv = gptr(J->adj) + (int64_t)((n + 1) & 1) * fstride;
+        kap = gptr(J->grad);
+        out = gptr(J->grad);
+    } else if constexpr (ADJ) {
         cur = gptr(J->adj) + (int64_t)((n + 1) & 1) * fstride;
         prv = gptr(J->adj) + (int64_t)(n & 1) * fstride;
         out = gptr(J->adj) + (int64_t)(n & 1) * fstride;
-        accum = J->accumulate && n <= J->nt - 1;
-        fwd = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
-        grad = gptr(J->grad);
+        if constexpr (FUSED) {
+            fwd = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
+            grad = gptr(J->grad);
+        }
     } else {
         cur = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
         prv = gptr(J->ring) + (int64_t)mod_pos(n - 1, J->R) * fstride;
         out = gptr(J->ring) + (int64_t)mod_pos(n + 1, J->R) * fstride;
     }
-    const gfloat *kap = gptr(J->kappa);
     const float eta_dt = J->eta_dt;
     const int pbytes = (int)(plane * (int64_t)sizeof(float));
 
@@ -313,7 +330,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
 
     // ---- prologue: queue slots 0..2M hold planes z0-M .. z0+M; plane z0 in LDS
     float q[RY][Q];
-    float f[ADJ ? RY : 1][ADJ ? Q : 1];
+    float f[FUSED ? RY : 1][FUSED ? Q : 1];
     float hy[HQ ? NYH : 1][HQ ? Q : 1], hx[HQ ? NXH : 1][HQ ? Q : 1];
     if constexpr (HQ) {
         // halo ring: slot s holds the halos of plane z0 - M + s (s = M+1 .. 2M now)
@@ -333,10 +350,10 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
             q[i][s] = ldb(pc, roff[i]);
-            if constexpr (ADJ) f[i][s] = ldb(pf, roff[i]);
+            if constexpr (FUSED) f[i][s] = ldb(pf, roff[i]);
         }
     }
-    float kv[RY], pv[RY], gv[ADJ ? RY : 1];
+    float kv[RY], pv[RY], gv[FUSED ? RY : 1];
     {
         const rsrc_t pk = plane_rsrc(kap, z0 + M, plane, pbytes);
         const rsrc_t pp = plane_rsrc(prv, z0 + M, plane, pbytes);
@@ -344,28 +361,28 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         for (int i = 0; i < RY; ++i) {
             kv[i] = ldb(pk, roff[i]);
             pv[i] = ldb(pp, roff[i]);
-            if constexpr (ADJ) gv[i] = accum ? ldb(plane_rsrc(grad, z0 + M, plane, pbytes), roff[i]) : 0.f;
+            if constexpr (FUSED) gv[i] = accum ? ldb(plane_rsrc(grad, z0 + M, plane, pbytes), roff[i]) : 0.f;
         }
         const rsrc_t pc = plane_rsrc(cur, z0 + M, plane, pbytes);
         const rsrc_t pf = plane_rsrc(fwd, z0 + M, plane, pbytes);
         float *L = sp + (z0 & 1) * LS;
-        float *LF = ADJ ? sf + (z0 & 1) * LS : nullptr;
+        float *LF = FUSED ? sf + (z0 & 1) * LS : nullptr;
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
             L[(M + wv * RY + i) * LX + M + lane] = q[i][M];
-            if constexpr (ADJ) LF[(M + wv * RY + i) * LX + M + lane] = f[i][M];
+            if constexpr (FUSED) LF[(M + wv * RY + i) * LX + M + lane] = f[i][M];
         }
 #pragma unroll
         for (int h = 0; h < NYH; ++h)
             if (hyl[h] >= 0) {
                 L[hyl[h]] = ldb(pc, hyo[h]);
-                if constexpr (ADJ) LF[hyl[h]] = ldb(pf, hyo[h]);
+                if constexpr (FUSED) LF[hyl[h]] = ldb(pf, hyo[h]);
             }
 #pragma unroll
         for (int h = 0; h < NXH; ++h)
             if (hxl[h] >= 0) {
                 L[hxl[h]] = ldb(pc, hxo[h]);
-                if constexpr (ADJ) LF[hxl[h]] = ldb(pf, hxo[h]);
+                if constexpr (FUSED) LF[hxl[h]] = ldb(pf, hxo[h]);
             }
     }
     __syncthreads();
@@ -378,7 +395,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             const bool more = z + 1 < z1;
             // ---- prefetch plane z+1 (queue front z+1+M, kappa', previous level, halos)
             float nq[RY], nk[RY], np[RY], nhy[NYH], nhx[NXH];
-            float nfq[ADJ ? RY : 1], ng[ADJ ? RY : 1], nfy[ADJ ? NYH : 1], nfx[ADJ ? NXH : 1];
+            float nfq[FUSED ? RY : 1], ng[FUSED ? RY : 1], nfy[FUSED ? NYH : 1], nfx[FUSED ? NXH : 1];
             if (more) {
                 const rsrc_t pq = plane_rsrc(cur, z + 1 + 2 * M, plane, pbytes);
                 const rsrc_t pk = plane_rsrc(kap, z + 1 + M, plane, pbytes);
@@ -395,7 +412,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                 for (int h = 0; h < NYH; ++h) nhy[h] = ldb(phq, hyo[h]);
 #pragma unroll
                 for (int h = 0; h < NXH; ++h) nhx[h] = ldb(phq, hxo[h]);
-                if constexpr (ADJ) {
+                if constexpr (FUSED) {
                     const rsrc_t fq = plane_rsrc(fwd, z + 1 + 2 * M, plane, pbytes);
                     const rsrc_t fh = plane_rsrc(fwd, z + 1 + M, plane, pbytes);
                     const rsrc_t pg = plane_rsrc(grad, z + 1 + M, plane, pbytes);
@@ -412,7 +429,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             }
             // ---- plane z
             const float *L = sp + (z & 1) * LS;
-            const float *LF = ADJ ? sf + (z & 1) * LS : nullptr;
+            const float *LF = FUSED ? sf + (z & 1) * LS : nullptr;
             const rsrc_t po = plane_rsrc(out, z + M, plane, pbytes);
             const rsrc_t pg = plane_rsrc(grad, z + M, plane, pbytes);
             const int dz = sponge_depth(z, nz, nb);
@@ -437,16 +454,23 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                                     ((q[i][(k + M + m) % Q] - pc) + (q[i][(k + M - m) % Q] - pc));
                     acc = fmaf(W.c[m], d, acc);
                 }
-                res[i] = fmaf(kv[i], acc, 2.f * pc);
+                // imaging: g + psi^{k+1} * L'p^k (kv holds g, pv psi^{k+1}),
+                // the same operation as the fused kernel's
+                res[i] = IMG ? fmaf(pv[i], acc, kv[i]) : fmaf(kv[i], acc, 2.f * pc);
             }
             if (src_blk && z == J->src_z) {
 #pragma unroll
                 for (int i = 0; i < RY; ++i) res[i] += i == src_row ? srcv : 0.f;
             }
 #pragma unroll
-            for (int i = 0; i < RY; ++i)
-                if (act[i]) stb_stream(po, roff[i], leapfrog(res[i], pv[i], dxy2[i] + dz * dz, eta_dt));
-            if constexpr (ADJ) {
+            for (int i = 0; i < RY; ++i) {
+                if constexpr (IMG) {
+                    if (act[i]) stb_stream(po, roff[i], res[i]);
+                } else {
+                    if (act[i]) stb_stream(po, roff[i], leapfrog(res[i], pv[i], dxy2[i] + dz * dz, eta_dt));
+                }
+            }
+            if constexpr (FUSED) {
                 if (accum) {
 #pragma unroll
                     for (int i = 0; i < RY; ++i) {
@@ -476,14 +500,14 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             // ---- rotate to plane z+1 and stage it in the other LDS buffer
             if (more) {
                 float *Ln = sp + ((z + 1) & 1) * LS;
-                float *LFn = ADJ ? sf + ((z + 1) & 1) * LS : nullptr;
+                float *LFn = FUSED ? sf + ((z + 1) & 1) * LS : nullptr;
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
                     q[i][k] = nq[i];   // slot k held plane z - M
                     kv[i] = nk[i];
                     pv[i] = np[i];
                     Ln[(M + wv * RY + i) * LX + M + lane] = q[i][(k + M + 1) % Q];
-                    if constexpr (ADJ) {
+                    if constexpr (FUSED) {
                         f[i][k] = nfq[i];
                         gv[i] = ng[i];
                         LFn[(M + wv * RY + i) * LX + M + lane] = f[i][(k + M + 1) % Q];
@@ -498,7 +522,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                         } else {
                             Ln[hyl[h]] = nhy[h];
                         }
-                        if constexpr (ADJ) LFn[hyl[h]] = nfy[h];
+                        if constexpr (FUSED) LFn[hyl[h]] = nfy[h];
                     }
 #pragma unroll
                 for (int h = 0; h < NXH; ++h)
@@ -509,7 +533,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                         } else {
                             Ln[hxl[h]] = nhx[h];
                         }
-                        if constexpr (ADJ) LFn[hxl[h]] = nfx[h];
+                        if constexpr (FUSED) LFn[hxl[h]] = nfx[h];
                     }
             }
             __syncthreads();
@@ -918,16 +942,49 @@ void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st)
     hipLaunchKernelGGL(k_vstats, dim3(vstats_blocks()), dim3(256), 0, st, v, n, partial);
 }
 
+// The 16th-order adjoint runs as two single-field passes (imaging condition,
+// then the psi update): the fused kernel carries two 17-plane queues at 2
+// waves per SIMD, each pass one queue at 4 (300 vs 2 x ~115 us per step on a
+// 304^3 grid).  Both compute bitwise the same values.  At 8th order the fused
+// kernel is as fast as the two passes (207 vs 106 + 99 us) and stays.
+template <int M>
+constexpr bool kSplitAdjoint = M >= 8;
+
 template <int M, int NW, int RY>
 static void launch_3d(bool adj, const Job *jobs, const int *prefix, int njobs, int step,
                       int ttiles, int grid, int remap, hipStream_t st)
 {
-    if (adj)
-        hipLaunchKernelGGL((k_step3d<M, true, NW, RY>), dim3(grid), dim3(64 * NW), 0, st, jobs,
-                           prefix, njobs, step, ttiles, remap);
-    else
-        hipLaunchKernelGGL((k_step3d<M, false, NW, RY>), dim3(grid), dim3(64 * NW), 0, st, jobs,
-                           prefix, njobs, step, ttiles, remap);
+    const dim3 g(grid), b(64 * NW);
+    if (!adj) {
+        hipLaunchKernelGGL((k_step3d<M, kFwd, NW, RY>), g, b, 0, st, jobs, prefix, njobs, step,
+                           ttiles, remap);
+    } else if constexpr (kSplitAdjoint<M>) {
+        // the imaging pass reads psi^{k+1} and p^k, which the psi pass leaves intact
+        hipLaunchKernelGGL((k_step3d<M, kImage, NW, RY>), g, b, 0, st, jobs, prefix, njobs,
+                           step, ttiles, remap);
+        hipLaunchKernelGGL((k_step3d<M, kAdjPsi, NW, RY>), g, b, 0, st, jobs, prefix, njobs,
+                           step, ttiles, remap);
+    } else {
+        hipLaunchKernelGGL((k_step3d<M, kAdj, NW, RY>), g, b, 0, st, jobs, prefix, njobs, step,
+                           ttiles, remap);
+    }
+}
+
+template <int M, int NW, int RY>
+static hipError_t occupancy_3d(int *n, bool adj)
+{
+    const int t = 64 * NW;
+    if (!adj) return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_step3d<M, kFwd, NW, RY>, t, 0);
+    if constexpr (!kSplitAdjoint<M>) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_step3d<M, kAdj, NW, RY>, t, 0);
+    } else {
+        int a = 0, c = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_step3d<M, kAdjPsi, NW, RY>, t, 0);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_step3d<M, kImage, NW, RY>, t, 0);
+        *n = a < c ? a : c;
+        return e;
+    }
 }
 
 template <int M>
@@ -959,15 +1016,9 @@ static int occupancy_m(int ndim, int nw, bool adj)
     int n = 0;
     hipError_t e = hipSuccess;
     if (ndim == 3) {
-        if (nw == 8)
-            e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, true, 8, 4>, 512, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, false, 8, 4>, 512, 0);
-        else if (nw == 42)
-            e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, true, 4, 2>, 256, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, false, 4, 2>, 256, 0);
-        else
-            e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, true, 4, 4>, 256, 0)
-                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step3d<M, false, 4, 4>, 256, 0);
+        if (nw == 8) e = occupancy_3d<M, 8, 4>(&n, adj);
+        else if (nw == 42) e = occupancy_3d<M, 4, 2>(&n, adj);
+        else e = occupancy_3d<M, 4, 4>(&n, adj);
     } else {
         e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step2d<M, true>, 64, 0)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step2d<M, false>, 64, 0);
