@@ -13,11 +13,12 @@
 // Design for CDNA4 (the paper's MXU band-matrix formulation does not apply:
 // the star stencil is banded, not a dense contraction, and the step is HBM
 // bound at 16 algorithmic bytes per cell-update):
-//  * 3-D: 256-thread blocks own a 64 (x) x 16 (y) column of the grid over a
-//    chunk of z planes.  Each thread keeps a register queue of 2M+1 planes
-//    for the z-derivative (z marching), the current xy plane with its M-cell
-//    halo is staged in LDS for the x and y derivatives, and each thread owns
-//    4 consecutive y rows so y-neighbours are reused from LDS.
+//  * 3-D: 256-thread blocks own a 64 (x) x 16 (y) column of the grid (64 x 8
+//    at 16th order and in the adjoint) over a chunk of z planes.  Each thread
+//    keeps a register queue of 2M+1 planes for the z-derivative (z marching),
+//    the current xy plane with its M-cell halo is staged in LDS for the x and
+//    y derivatives, and each thread owns 4 (or 2) consecutive y rows so
+//    y-neighbours are reused from LDS.
 //  * 2-D: one wavefront per block, 64 columns marching down a chunk of rows.
 //  * Each wavefront reads and writes whole aligned 256-byte row segments.
 //  * Blocks are remapped so that each XCD (one L2 each) gets a contiguous
@@ -180,13 +181,14 @@ __device__ __forceinline__ gfloat *plane_ptr(gfloat *f, int zmem, int64_t plane)
 }
 
 // --------------------------------------------------------------- 3-D step
-// One block: 4 wavefronts, a 64 (x) x 16 (y) tile, marching a chunk of z.
-// Per plane z: the LDS buffer (z & 1) holds plane z of the propagated field
+// One block: NW wavefronts of RY rows each, a 64 (x) x NW*RY (y) tile,
+// marching a chunk of z.  Per plane z: the LDS buffer (z & 1) holds plane z of the propagated field
 // with an M-cell halo; registers hold the z-queue (planes z-M .. z+M, in a
 // ring indexed by the unrolled phase k, so no register moves), kappa' and
 // the previous level.  While plane z is computed, plane z+1 is already being
 // loaded (the next queue front, kappa', previous level, halos), and written
 // to the other LDS buffer afterwards: one barrier per plane.
+//
 // Step modes: the forward step; the adjoint step with the imaging condition
 // fused in (two stencil fields); and the adjoint as two single-field passes,
 // the psi update alone and the imaging condition g += psi^{k+1} * L'p^k
