@@ -210,6 +210,68 @@ def gradient3d_section(dev, nt, every, order=8):
             "gradient_over_forward": round(tg / tf, 3), "misfit": mis}
 
 
+def salt3d_section(dev, nt, budget="40e9"):
+    """3-D salt workload (512x512x256 model + 24-cell sponge, 560x560x304
+    padded, 8th order, 512x512 receivers): the forward's rate, and the
+    gradient with binomial (revolve) checkpointing under a snapshot budget,
+    against every-50 snapshots."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_1912_08063_amd import _lib, api, workloads as wl
+    P = wl.salt_3d(nt=nt)
+    t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
+    v, w = t(P.v, torch.float32), t(P.wavelet, torch.float32)
+    s, r = t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
+    cfg = api.Config(dt=P.dt, dx=P.dx, order=P.order, nsponge=P.nb, eta_max=P.eta_max,
+                     ckpt="revolve:%s" % budget)
+    obs = torch.empty((1, nt, P.nrec), dtype=torch.float32, device=dev)
+    ws = api.Workspace()
+    api.forward(v, w, s, r, cfg, workspace=ws, out=obs)            # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    api.forward(v, w, s, r, cfg, workspace=ws, out=obs)            # also the observed data
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    log("salt forward: %d steps in %.3f s" % (nt, tf))
+    v0 = t(P.v_start, torch.float32)
+    del ws
+    out = {"workload": "3-D FWI, salt model 512x512x256 + 24-cell sponge (560x560x304 padded), "
+                       "8th order, %d steps, 512x512 receivers" % nt,
+           "forward_s": round(tf, 4),
+           "forward_Gcell_updates_per_s": round(P.padded_cells * nt / tf / 1e9, 3),
+           "forward_hbm_frac": round(BYTES_PER_UPDATE * P.padded_cells * nt / tf / 1e9
+                                     / HBM_PEAK_GBS, 4)}
+    # bytes per snapshot slot (two levels of the padded, framed field), from
+    # the gradient's workspace size at one and at two slots
+    prob = api.make_problem(v0, nt, cfg, 1, P.nrec)
+    wsb = [_lib.fwi_workspace_bytes(prob, _lib.MODE_GRADIENT, api.parse_ckpt("revolve:%d" % k))
+           for k in (1, 2)]
+    slot_bytes = wsb[1] - wsb[0]
+    slots = int(float(budget)) // slot_bytes
+    fwd_steps = _lib.fwi_revolve_schedule(nt, slots, with_actions=False)[1]
+    for spec in ("revolve:%s" % budget, "every:50"):
+        cg = dataclasses.replace(cfg, ckpt=spec)
+        wg = api.Workspace()
+        api.gradient(v0, obs, w, s, r, cg, workspace=wg)           # warm-up (and sizing)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mis, dv = api.gradient(v0, obs, w, s, r, cg, workspace=wg)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        log("salt gradient %s: %.3f s" % (spec, tg))
+        key = spec.split(":")[0]
+        out[key] = {"gradient_s": round(tg, 4), "gradient_over_forward": round(tg / tf, 3),
+                    "misfit": mis}
+        del wg, dv
+        torch.cuda.empty_cache()
+    out["revolve"].update(slots=slots, snapshot_bytes=slots * slot_bytes,
+                          forward_steps=fwd_steps, adjoint_steps=nt)
+    return out
+
+
 def serve_section(nreq, scale, chunk):
     """Serving (reduced grid/step scale): Poisson stream of mixed 2-D/3-D forward and
     gradient requests at 0.8x the saturated rate; continuous batching vs one
@@ -248,10 +310,11 @@ def main():
     ap.add_argument("--nt", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="forward,forward16,gradient,gradient3d,serve",
+    ap.add_argument("--sections", default="forward,forward16,gradient,gradient3d,salt3d,serve",
                     help="comma list of: forward (headline), forward16 (16th order), gradient "
-                         "(2-D, 32 shots), gradient3d (headline geometry), serve (request "
-                         "stream)")
+                         "(2-D, 32 shots), gradient3d (headline geometry), salt3d (salt "
+                         "model, revolve), serve (request stream)")
+    ap.add_argument("--salt-nt", type=int, default=3000)
     ap.add_argument("--grad-nt", type=int, default=3000)
     ap.add_argument("--grad-shots", type=int, default=32)
     ap.add_argument("--grad3d-nt", type=int, default=600)
@@ -367,6 +430,8 @@ def main():
         out["forward16"] = forward16_section(dev, args.fwd16_nt)
     if "gradient3d" in sections:
         out["gradient3d"] = gradient3d_section(dev, args.grad3d_nt, 50, args.grad3d_order)
+    if "salt3d" in sections:
+        out["salt3d"] = salt3d_section(dev, args.salt_nt)
     if "serve" in sections:
         out["serving"] = serve_section(args.serve_requests, args.serve_scale, 50)
     if not args.no_cpu_baseline:
