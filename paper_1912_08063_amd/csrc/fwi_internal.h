@@ -65,4 +65,15 @@ struct Job {
     const float *res;      // [nt][nrec] adjoint source
 };
 
+// Forward levels that a launch finds in the snapshot store instead of the
+// ring: level lev[i] is field fld[i] of each job's store (slot s holds fields
+// 2s and 2s+1).  Binomial checkpointing uses it to read a restored state, or
+// write a state it is about to snapshot, in place instead of copying it.
+// Unused entries hold kNoLevel.
+constexpr int32_t kNoLevel = -2147483647 - 1;
+struct LevelMap {
+    int32_t lev[3] = {kNoLevel, kNoLevel, kNoLevel};
+    int32_t fld[3] = {0, 0, 0};
+};
+
 }  // namespace fwi

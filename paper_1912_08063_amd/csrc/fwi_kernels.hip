@@ -98,11 +98,22 @@ __device__ __forceinline__ int xcd_remap(int b, int T)
 
 __device__ __forceinline__ int mod_pos(int a, int R) { int m = a % R; return m < 0 ? m + R : m; }
 
+// Field of forward level L: the ring slot L mod R, or a snapshot field the
+// level map names (block-uniform, scalar).
+__device__ __forceinline__ float *level_ptr(const Job *__restrict__ J, const LevelMap &lm, int L)
+{
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        if (lm.lev[i] == L) return J->snap + (int64_t)lm.fld[i] * J->fstride;
+    return J->ring + (int64_t)mod_pos(L, J->R) * J->fstride;
+}
+
 // Receiver sampling: traces[n-1][r] = p^n[rec_r] (level n is read-only here).
-__device__ __forceinline__ void gather_block(const Job *__restrict__ J, int r, int n)
+__device__ __forceinline__ void gather_block(const Job *__restrict__ J, const LevelMap &lm, int r,
+                                             int n)
 {
     if (!J->record || n < 1 || n > J->nt || r >= J->nrec) return;
-    const float *cur = J->ring + (int64_t)mod_pos(n, J->R) * J->fstride;
+    const float *cur = level_ptr(J, lm, n);
     J->traces[(int64_t)(n - 1) * J->nrec + r] = cur[J->rec_off[r]];
 }
 
@@ -198,7 +209,7 @@ enum StepMode { kFwd = 0, kAdj = 1, kAdjPsi = 2, kImage = 3 };
 template <int M, int MODE, int NW, int RY>
 __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs,
                                                 const int *__restrict__ prefix, int njobs,
-                                                int step, int ttiles, int remap)
+                                                int step, int ttiles, int remap, LevelMap lm)
 {
     constexpr int TX = kTileX, TY = RY * NW, NT = 64 * NW;
     constexpr int LX = TX + 2 * M, LY = TY + 2 * M, Q = 2 * M + 1, LS = LY * LX;
@@ -227,7 +238,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         const int gb = b - ttiles;
         const int j = find_job(prefix + njobs + 1, njobs, gb);
         const Job *J = jobs + j;
-        gather_block(J, (gb - prefix[njobs + 1 + j]) * blockDim.x + tid, J->n0 + step);
+        gather_block(J, lm, (gb - prefix[njobs + 1 + j]) * blockDim.x + tid, J->n0 + step);
         return;
     }
     if (remap) b = xcd_remap(b, ttiles);
@@ -255,7 +266,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     const bool accum = ADJ && J->accumulate && n <= J->nt - 1;
     if constexpr (IMG) {
         if (!accum) return;
-        cur = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
+        cur = gptr(level_ptr(J, lm, n));
         prv = gptr(J->adj) + (int64_t)((n + 1) & 1) * fstride;
         kap = gptr(J->grad);
         out = gptr(J->grad);
@@ -264,13 +275,13 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         prv = gptr(J->adj) + (int64_t)(n & 1) * fstride;
         out = gptr(J->adj) + (int64_t)(n & 1) * fstride;
         if constexpr (FUSED) {
-            fwd = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
+            fwd = gptr(level_ptr(J, lm, n));
             grad = gptr(J->grad);
         }
     } else {
-        cur = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
-        prv = gptr(J->ring) + (int64_t)mod_pos(n - 1, J->R) * fstride;
-        out = gptr(J->ring) + (int64_t)mod_pos(n + 1, J->R) * fstride;
+        cur = gptr(level_ptr(J, lm, n));
+        prv = gptr(level_ptr(J, lm, n - 1));
+        out = gptr(level_ptr(J, lm, n + 1));
     }
     const float eta_dt = J->eta_dt;
     const int pbytes = (int)(plane * (int64_t)sizeof(float));
@@ -551,7 +562,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
 template <int M, bool ADJ>
 __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
                                                const int *__restrict__ prefix, int njobs,
-                                               int step, int ttiles, int remap)
+                                               int step, int ttiles, int remap, LevelMap lm)
 {
     constexpr int TX = kTileX, LX = TX + 2 * M, Q = 2 * M + 1;
     constexpr Weights<M> W{};
@@ -566,7 +577,7 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
         const int gb = b - ttiles;
         const int j = find_job(prefix + njobs + 1, njobs, gb);
         const Job *J = jobs + j;
-        gather_block(J, (gb - prefix[njobs + 1 + j]) * blockDim.x + lane, J->n0 + step);
+        gather_block(J, lm, (gb - prefix[njobs + 1 + j]) * blockDim.x + lane, J->n0 + step);
         return;
     }
     if (remap) b = xcd_remap(b, ttiles);
@@ -593,12 +604,12 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
         prv = gptr(J->adj) + (int64_t)(n & 1) * fstride;
         out = gptr(J->adj) + (int64_t)(n & 1) * fstride;
         accum = J->accumulate && n <= J->nt - 1;
-        fwd = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
+        fwd = gptr(level_ptr(J, lm, n));
         grad = gptr(J->grad);
     } else {
-        cur = gptr(J->ring) + (int64_t)mod_pos(n, J->R) * fstride;
-        prv = gptr(J->ring) + (int64_t)mod_pos(n - 1, J->R) * fstride;
-        out = gptr(J->ring) + (int64_t)mod_pos(n + 1, J->R) * fstride;
+        cur = gptr(level_ptr(J, lm, n));
+        prv = gptr(level_ptr(J, lm, n - 1));
+        out = gptr(level_ptr(J, lm, n + 1));
     }
     const gfloat *kap = gptr(J->kappa);
     const float eta_dt = J->eta_dt;
@@ -753,13 +764,20 @@ __global__ void k_fill(float4 *__restrict__ p, int64_t n4, float val)
 }
 
 // Snapshots of a leapfrog state (levels t and t-1) for every job of the table.
-// dir 0: ring -> snap[slot]; 1: snap[slot] -> ring; 2: zero the two levels (t = 0).
-__global__ void k_snapshot(const Job *__restrict__ jobs, int slot, int time, int dir)
+// dir 0: level -> snap[slot] (the level where the map puts it); 1: snap[slot]
+// -> ring; 2: zero the two levels in the ring (t = 0).  mask bit w selects
+// level t - w.
+__global__ void k_snapshot(const Job *__restrict__ jobs, int slot, int time, int dir, int mask,
+                           LevelMap lm)
 {
     const Job *J = jobs + (blockIdx.y >> 1);
     const int which = blockIdx.y & 1;
-    float4 *r = reinterpret_cast<float4 *>(J->ring + (int64_t)mod_pos(time - which, J->R) * J->fstride);
+    if (!((mask >> which) & 1)) return;
+    float4 *r = reinterpret_cast<float4 *>(
+        dir == 0 ? level_ptr(J, lm, time - which)
+                 : J->ring + (int64_t)mod_pos(time - which, J->R) * J->fstride);
     float4 *s = reinterpret_cast<float4 *>(J->snap + (int64_t)(2 * slot + which) * J->fstride);
+    if (r == s) return;
     const int64_t n4 = J->fstride / 4;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -771,11 +789,11 @@ __global__ void k_snapshot(const Job *__restrict__ jobs, int slot, int time, int
 
 // Final receiver sampling (level n = n0 + step).
 __global__ void k_gather(const Job *__restrict__ jobs, const int *__restrict__ gprefix,
-                         int njobs, int step)
+                         int njobs, int step, LevelMap lm)
 {
     const int j = find_job(gprefix, njobs, blockIdx.x);
     const Job *J = jobs + j;
-    gather_block(J, (blockIdx.x - gprefix[j]) * blockDim.x + threadIdx.x, J->n0 + step);
+    gather_block(J, lm, (blockIdx.x - gprefix[j]) * blockDim.x + threadIdx.x, J->n0 + step);
 }
 
 // Adjoint source: psi'^k[rec] += kappa'[rec] * res[k-1][rec] (alpha = 1 on the
@@ -954,21 +972,21 @@ constexpr bool kSplitAdjoint = M >= 8;
 
 template <int M, int NW, int RY>
 static void launch_3d(bool adj, const Job *jobs, const int *prefix, int njobs, int step,
-                      int ttiles, int grid, int remap, hipStream_t st)
+                      int ttiles, int grid, int remap, const LevelMap &lm, hipStream_t st)
 {
     const dim3 g(grid), b(64 * NW);
     if (!adj) {
         hipLaunchKernelGGL((k_step3d<M, kFwd, NW, RY>), g, b, 0, st, jobs, prefix, njobs, step,
-                           ttiles, remap);
+                           ttiles, remap, lm);
     } else if constexpr (kSplitAdjoint<M>) {
         // the imaging pass reads psi^{k+1} and p^k, which the psi pass leaves intact
         hipLaunchKernelGGL((k_step3d<M, kImage, NW, RY>), g, b, 0, st, jobs, prefix, njobs,
-                           step, ttiles, remap);
+                           step, ttiles, remap, lm);
         hipLaunchKernelGGL((k_step3d<M, kAdjPsi, NW, RY>), g, b, 0, st, jobs, prefix, njobs,
-                           step, ttiles, remap);
+                           step, ttiles, remap, lm);
     } else {
         hipLaunchKernelGGL((k_step3d<M, kAdj, NW, RY>), g, b, 0, st, jobs, prefix, njobs, step,
-                           ttiles, remap);
+                           ttiles, remap, lm);
     }
 }
 
@@ -991,23 +1009,24 @@ static hipError_t occupancy_3d(int *n, bool adj)
 
 template <int M>
 static void launch_step_m(int ndim, int nw, bool adj, const Job *jobs, const int *prefix,
-                          int njobs, int step, int ttiles, int gblocks, int remap, hipStream_t st)
+                          int njobs, int step, int ttiles, int gblocks, int remap,
+                          const LevelMap &lm, hipStream_t st)
 {
     const int grid = ttiles + (adj ? 0 : gblocks);
     if (grid <= 0) return;
     if (ndim == 3) {
         switch (nw) {   // wavefronts per block x rows per thread
-        case 8: launch_3d<M, 8, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, st); break;
-        case 42: launch_3d<M, 4, 2>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, st); break;
-        default: launch_3d<M, 4, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, st); break;
+        case 8: launch_3d<M, 8, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, lm, st); break;
+        case 42: launch_3d<M, 4, 2>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, lm, st); break;
+        default: launch_3d<M, 4, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, lm, st); break;
         }
     } else {
         if (adj)
             hipLaunchKernelGGL((k_step2d<M, true>), dim3(grid), dim3(64), 0, st, jobs, prefix,
-                               njobs, step, ttiles, remap);
+                               njobs, step, ttiles, remap, lm);
         else
             hipLaunchKernelGGL((k_step2d<M, false>), dim3(grid), dim3(64), 0, st, jobs, prefix,
-                               njobs, step, ttiles, remap);
+                               njobs, step, ttiles, remap, lm);
     }
 }
 
@@ -1040,13 +1059,14 @@ int step_blocks_per_cu(int ndim, int M, int nw, bool adj)
 }
 
 void launch_step(int ndim, int M, int nw, bool adj, const Job *jobs, const int *prefix,
-                 int njobs, int step, int ttiles, int gblocks, int remap, hipStream_t st)
+                 int njobs, int step, int ttiles, int gblocks, int remap, const LevelMap &lm,
+                 hipStream_t st)
 {
     switch (M) {
-    case 1: launch_step_m<1>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
-    case 2: launch_step_m<2>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
-    case 4: launch_step_m<4>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
-    case 8: launch_step_m<8>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, st); break;
+    case 1: launch_step_m<1>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, lm, st); break;
+    case 2: launch_step_m<2>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, lm, st); break;
+    case 4: launch_step_m<4>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, lm, st); break;
+    case 8: launch_step_m<8>(ndim, nw, adj, jobs, prefix, njobs, step, ttiles, gblocks, remap, lm, st); break;
     default: break;
     }
 }
@@ -1074,18 +1094,18 @@ void launch_fill(float *p, int64_t n, float val, hipStream_t st)
 }
 
 void launch_snapshot(const Job *jobs, int njobs, int64_t fstride, int slot, int time, int dir,
-                     hipStream_t st)
+                     int mask, const LevelMap &lm, hipStream_t st)
 {
     hipLaunchKernelGGL(k_snapshot, dim3(grid_for(fstride / 4, 256, 4096), 2 * njobs), dim3(256),
-                       0, st, jobs, slot, time, dir);
+                       0, st, jobs, slot, time, dir, mask, lm);
 }
 
 void launch_gather(const Job *jobs, const int *gprefix, int njobs, int gblocks, int threads,
-                   int step, hipStream_t st)
+                   int step, const LevelMap &lm, hipStream_t st)
 {
     if (gblocks > 0)
         hipLaunchKernelGGL(k_gather, dim3(gblocks), dim3(threads), 0, st, jobs, gprefix, njobs,
-                           step);
+                           step, lm);
 }
 
 void launch_adj_inject(const Job *jobs, const int *gprefix, int njobs, int gblocks, int threads,

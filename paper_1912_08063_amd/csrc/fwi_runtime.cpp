@@ -24,15 +24,16 @@
 
 namespace fwi {
 void launch_step(int ndim, int M, int nw, bool adj, const Job *jobs, const int *prefix,
-                 int njobs, int step, int ttiles, int gblocks, int remap, hipStream_t st);
+                 int njobs, int step, int ttiles, int gblocks, int remap, const LevelMap &lm,
+                 hipStream_t st);
 void launch_prep_kappa(const float *v, float *kappa, int M, int gy, int nz, int ny, int nx,
                        int pitch, int nya, int nb, int nzm, int nym, int nxm, int64_t total,
                        float dt_dx, hipStream_t st);
 void launch_fill(float *p, int64_t n, float val, hipStream_t st);
 void launch_snapshot(const Job *jobs, int njobs, int64_t fstride, int slot, int time, int dir,
-                     hipStream_t st);
+                     int mask, const LevelMap &lm, hipStream_t st);
 void launch_gather(const Job *jobs, const int *gprefix, int njobs, int gblocks, int threads,
-                   int step, hipStream_t st);
+                   int step, const LevelMap &lm, hipStream_t st);
 void launch_adj_inject(const Job *jobs, const int *gprefix, int njobs, int gblocks, int threads,
                        int step, hipStream_t st);
 int misfit_partials();
@@ -529,36 +530,152 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
     return FWI_OK;
 }
 
-// ------------------------------------------------------------ time loops
-int fwd_step(Ctx &c, int n, bool record)
-{
-    launch_step(c.g.ndim, c.g.M, c.nw, false, c.d_jobs, c.d_prefix, c.p->nshots, n, c.ttiles,
-                record ? c.gblocks : 0, c.remap, c.st);
-    return FWI_OK;
-}
-
-int adj_step(Ctx &c, int k)
-{
-    launch_step(c.g.ndim, c.g.M, c.nw_adj, true, c.d_jobs, c.d_prefix + 2 * (c.p->nshots + 1),
-                c.p->nshots, -k, c.atiles, 0, c.remap, c.st);
-    launch_adj_inject(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
-                      c.gthreads, -k, c.st);
-    return FWI_OK;
-}
-
-int snapshot(Ctx &c, int slot, int time, int dir)
-{
-    if (dir != 2 && (slot < 0 || slot >= c.po.nsnap))
-        return fail(FWI_EINVAL, "internal: snapshot slot %d of %d", slot, c.po.nsnap);
-    launch_snapshot(c.d_jobs, c.p->nshots, c.g.fstride, slot, time, dir, c.st);
-    return FWI_OK;
-}
-
 #define TRY(x)                   \
     do {                         \
         const int s_ = (x);      \
         if (s_) return s_;       \
     } while (0)
+
+// ------------------------------------------------------------ time loops
+int fwd_step(Ctx &c, int n, bool record, const LevelMap &lm = LevelMap{})
+{
+    launch_step(c.g.ndim, c.g.M, c.nw, false, c.d_jobs, c.d_prefix, c.p->nshots, n, c.ttiles,
+                record ? c.gblocks : 0, c.remap, lm, c.st);
+    return FWI_OK;
+}
+
+int adj_step(Ctx &c, int k, const LevelMap &lm = LevelMap{})
+{
+    launch_step(c.g.ndim, c.g.M, c.nw_adj, true, c.d_jobs, c.d_prefix + 2 * (c.p->nshots + 1),
+                c.p->nshots, -k, c.atiles, 0, c.remap, lm, c.st);
+    launch_adj_inject(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
+                      c.gthreads, -k, c.st);
+    return FWI_OK;
+}
+
+// dir 0: levels time, time-1 -> slot (read where lm puts them); 1: slot ->
+// ring; 2: zero levels 0, -1 in the ring.  mask bit w: level time - w.
+int snapshot(Ctx &c, int slot, int time, int dir, int mask = 3, const LevelMap &lm = LevelMap{})
+{
+    if (dir != 2 && (slot < 0 || slot >= c.po.nsnap))
+        return fail(FWI_EINVAL, "internal: snapshot slot %d of %d", slot, c.po.nsnap);
+    launch_snapshot(c.d_jobs, c.p->nshots, c.g.fstride, slot, time, dir, mask, lm, c.st);
+    return FWI_OK;
+}
+
+// Binomial checkpointing without snapshot copies.  A restore does not copy
+// the slot back into the ring: the following steps (or the adjoint step)
+// read the two levels from the slot.  The steps that produce the two levels
+// of a snapshot write them into the slot, and the steps after read them
+// there.  Held lists the live forward levels kept in snapshot fields; every
+// other level is in the ring.  A copy remains only where a snapshot follows
+// fewer than two steps, and FWI_REVOLVE_COPY=1 restores copies throughout.
+struct Held {
+    std::vector<std::pair<int, int>> at;   // (level, snapshot field 2s + w)
+
+    int field(int L) const
+    {
+        for (const auto &e : at)
+            if (e.first == L) return e.second;
+        return -1;
+    }
+    void put(int L, int f)
+    {
+        drop_if([L](const std::pair<int, int> &e) { return e.first == L; });
+        if (f >= 0) at.push_back({L, f});
+    }
+    void keep_from(int L)
+    {
+        drop_if([L](const std::pair<int, int> &e) { return e.first < L; });
+    }
+    bool uses_slot(int slot) const
+    {
+        for (const auto &e : at)
+            if (e.second / 2 == slot) return true;
+        return false;
+    }
+    template <class F>
+    void drop_if(F f)
+    {
+        at.erase(std::remove_if(at.begin(), at.end(), f), at.end());
+    }
+    // map entries for the listed levels that live in snapshot fields
+    LevelMap map(std::initializer_list<int> levels) const
+    {
+        LevelMap m;
+        int i = 0;
+        for (int L : levels) {
+            const int f = field(L);
+            if (f >= 0 && i < 3) { m.lev[i] = L; m.fld[i] = f; ++i; }
+        }
+        return m;
+    }
+};
+
+bool revolve_copies()
+{
+    const char *e = getenv("FWI_REVOLVE_COPY");
+    return e && atoi(e) != 0;
+}
+
+// Forward step n -> n+1: levels n and n-1 read where they are held, level
+// n+1 written to snapshot field dst (-1: the ring).
+void rv_step(Ctx &c, Held &h, int n, bool record, int dst)
+{
+    LevelMap m = h.map({n, n - 1});
+    if (dst >= 0) {
+        int i = 0;
+        while (i < 3 && m.lev[i] != kNoLevel) ++i;
+        m.lev[i] = n + 1;   // i < 3: at most two entries above
+        m.fld[i] = dst;
+    }
+    fwd_step(c, n, record, m);
+    h.put(n + 1, dst);
+    h.keep_from(n);
+}
+
+// Advance cur -> to.  If a snapshot into slot `shot` (-1: none) follows at
+// time `to`, the steps producing levels to - 1 and to write into the slot,
+// unless a live level is held there.
+void rv_advance(Ctx &c, Held &h, int cur, int to, int shot, bool record)
+{
+    const bool direct = shot >= 0 && !revolve_copies() && !h.uses_slot(shot);
+    for (int n = cur; n < to; ++n) {
+        int dst = -1;
+        if (direct && n + 1 == to) dst = 2 * shot;
+        else if (direct && n + 1 == to - 1) dst = 2 * shot + 1;
+        rv_step(c, h, n, record, dst);
+    }
+}
+
+// Snapshot of levels t, t-1 into slot: copies what the steps did not write there.
+int rv_takeshot(Ctx &c, Held &h, int slot, int t)
+{
+    const int mask = (h.field(t) != 2 * slot ? 1 : 0) | (h.field(t - 1) != 2 * slot + 1 ? 2 : 0);
+    if (mask) TRY(snapshot(c, slot, t, 0, mask, h.map({t, t - 1})));
+    return FWI_OK;
+}
+
+// Restore of slot (time t): the levels stay in the slot.
+int rv_restore(Ctx &c, Held &h, int slot, int t)
+{
+    h.at.clear();
+    if (revolve_copies()) return snapshot(c, slot, t, 1);
+    h.put(t, 2 * slot);
+    h.put(t - 1, 2 * slot + 1);
+    return FWI_OK;
+}
+
+// Copies held levels back into the ring (field f holds level L).
+int rv_to_ring(Ctx &c, Held &h, int L)
+{
+    const int f = h.field(L);
+    if (f < 0) return FWI_OK;
+    TRY(snapshot(c, f / 2, L + (f & 1), 1, 1 << (f & 1)));
+    h.put(L, -1);
+    return FWI_OK;
+}
+
 
 void zero(float *p, uint64_t floats, hipStream_t st) { launch_fill(p, (int64_t)floats, 0.f, st); }
 
@@ -572,20 +689,35 @@ int forward_phase(Ctx &c, bool record)
         int64_t steps = 0;
         std::vector<Action> acts = revolve_schedule(nt, c.po.nsnap, &steps);
         c.slot_time.assign(std::max(c.po.nsnap, 1), -1);
+        // steps store only grid cells, so fields they write must start with
+        // a zero frame: the snapshot store is cleared once
+        if (!revolve_copies() && c.po.nsnap > 0)
+            zero(c.jobs[0].snap, 2 * fs * c.po.nsnap * c.p->nshots, c.st);
         int cur = 0;
-        for (const Action &a : acts) {
-            if (a.op == OP_ADJOINT) break;
+        Held h;
+        for (size_t i = 0; i < acts.size() && acts[i].op != OP_ADJOINT; ++i) {
+            const Action &a = acts[i];
             if (a.op == OP_ADVANCE) {
-                for (int n = cur; n < a.arg; ++n) fwd_step(c, n, record);
+                const bool shot = i + 1 < acts.size() && acts[i + 1].op == OP_TAKESHOT;
+                rv_advance(c, h, cur, a.arg, shot ? acts[i + 1].arg : -1, record);
                 cur = a.arg;
             } else if (a.op == OP_TAKESHOT) {
-                TRY(snapshot(c, a.arg, cur, 0));
+                TRY(rv_takeshot(c, h, a.arg, cur));
                 c.slot_time[a.arg] = cur;
             } else {
                 return fail(FWI_EINVAL, "revolve: unexpected action in the first sweep");
             }
         }
-        for (int n = cur; n < nt; ++n) fwd_step(c, n, record);
+        for (int n = cur; n < nt; ++n) rv_step(c, h, n, record, -1);
+        // the end state goes to the ring, where the backward sweep (possibly a
+        // separate call) starts
+        if (record)
+            launch_gather(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
+                          c.gthreads, nt, h.map({nt}), c.st);
+        TRY(rv_to_ring(c, h, nt));
+        TRY(rv_to_ring(c, h, nt - 1));
+        HIP_TRY(hipGetLastError());
+        return FWI_OK;
     } else {
         const int K = c.po.every;
         for (int n = 0; n < nt; ++n) {
@@ -596,7 +728,7 @@ int forward_phase(Ctx &c, bool record)
     }
     if (record)
         launch_gather(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
-                      c.gthreads, nt, c.st);
+                      c.gthreads, nt, LevelMap{}, c.st);
     HIP_TRY(hipGetLastError());
     return FWI_OK;
 }
@@ -621,22 +753,28 @@ int backward_phase(Ctx &c)
             else if (acts[i].op == OP_TAKESHOT) c.slot_time[acts[i].arg] = cur;
         }
         cur = nt;
+        Held h;   // the forward sweep left levels nt and nt-1 in the ring
         for (; i < acts.size(); ++i) {
             const Action &a = acts[i];
             switch (a.op) {
-            case OP_ADJOINT: adj_step(c, a.arg); break;
-            case OP_ADVANCE:
-                for (int n = cur; n < a.arg; ++n) fwd_step(c, n, false);
+            case OP_ADJOINT: adj_step(c, a.arg, h.map({a.arg})); break;
+            case OP_ADVANCE: {
+                const bool shot = i + 1 < acts.size() && acts[i + 1].op == OP_TAKESHOT;
+                rv_advance(c, h, cur, a.arg, shot ? acts[i + 1].arg : -1, false);
                 cur = a.arg;
                 break;
-            case OP_TAKESHOT: TRY(snapshot(c, a.arg, cur, 0)); c.slot_time[a.arg] = cur; break;
+            }
+            case OP_TAKESHOT:
+                TRY(rv_takeshot(c, h, a.arg, cur));
+                c.slot_time[a.arg] = cur;
+                break;
             case OP_RESTORE:
                 if (a.arg < 0 || a.arg >= (int)c.slot_time.size() || c.slot_time[a.arg] < 0)
                     return fail(FWI_EINVAL, "internal: restore of an empty slot");
                 cur = c.slot_time[a.arg];
-                TRY(snapshot(c, a.arg, cur, 1));
+                TRY(rv_restore(c, h, a.arg, cur));
                 break;
-            case OP_RESTART: TRY(snapshot(c, 0, 0, 2)); cur = 0; break;
+            case OP_RESTART: TRY(snapshot(c, 0, 0, 2)); h.at.clear(); cur = 0; break;
             default: return fail(FWI_EINVAL, "revolve: bad action");
             }
         }
@@ -707,7 +845,7 @@ int run_immediate(fwi_job *J, const JobOp &o)
     case JOP_RESTORE: return snapshot(c, o.slot, o.a, 1);
     case JOP_ZERO_STATE: return snapshot(c, 0, 0, 2);
     case JOP_GATHER:
-        launch_gather(c.d_jobs, c.d_prefix + 2, 1, c.gblocks, c.gthreads, o.a, c.st);
+        launch_gather(c.d_jobs, c.d_prefix + 2, 1, c.gblocks, c.gthreads, o.a, LevelMap{}, c.st);
         return FWI_OK;
     case JOP_MISFIT: {
         const int64_t n = (int64_t)J->prob.nt * J->prob.nrec;
@@ -1134,7 +1272,7 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
                 const int n = (int)g.table.size();
                 const int ttiles = g.tp.back(), gblocks = g.gp.back();
                 launch_step(g.ndim, g.M, g.nw, g.adj != 0, g.d_jobs, g.d_prefix, n, j, ttiles,
-                            g.adj ? 0 : gblocks, 1, st);
+                            g.adj ? 0 : gblocks, 1, LevelMap{}, st);
                 if (g.adj)
                     launch_adj_inject(g.d_jobs, g.d_prefix + n + 1, n, gblocks, g.gthreads, j, st);
             }

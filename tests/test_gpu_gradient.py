@@ -63,11 +63,28 @@ def test_checkpoint_policies_bitwise_identical():
         assert np.array_equal(dv, ref_dv), ck
 
 
-def test_3d_checkpoint_policies_bitwise_identical():
-    P, obs, v0 = _setup(wl.small_3d(shape=(20, 18, 66), nt=41, nrec=12), 1.5)
-    _, ref, _ = gpu_gradient(P, v0, obs, "all")
-    for ck in ["every:6", "revolve:2"]:
-        assert np.array_equal(gpu_gradient(P, v0, obs, ck)[1], ref), ck
+@pytest.mark.parametrize("order", [8, 16])
+def test_3d_checkpoint_policies_bitwise_identical(order):
+    P, obs, v0 = _setup(wl.small_3d(shape=(20, 18, 66), nt=41, nrec=12, order=order), 1.5)
+    ref_mis, ref, ref_tr = gpu_gradient(P, v0, obs, "all")
+    for ck in ["every:6", "revolve:1", "revolve:2", "revolve:5", "revolve:40"]:
+        mis, dv, tr = gpu_gradient(P, v0, obs, ck)
+        assert mis == ref_mis, ck
+        assert np.array_equal(tr, ref_tr), ck
+        assert np.array_equal(dv, ref), ck
+
+
+def test_revolve_without_copies_equals_copies(monkeypatch):
+    """Binomial checkpointing reads restored states from their slots and
+    writes snapshot states straight into them; FWI_REVOLVE_COPY=1 copies
+    instead.  Both give the same gradient and traces, bit for bit."""
+    P, obs, v0 = _setup(wl.small_3d(shape=(25, 30, 90), nt=75, nshots=2, nrec=15))
+    got = gpu_gradient(P, v0, obs, "revolve:4")
+    monkeypatch.setenv("FWI_REVOLVE_COPY", "1")
+    ref = gpu_gradient(P, v0, obs, "revolve:4")
+    assert got[0] == ref[0]
+    assert np.array_equal(got[2], ref[2])
+    assert np.array_equal(got[1], ref[1])
 
 
 def test_zero_residual_gives_zero_gradient():
