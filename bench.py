@@ -210,7 +210,7 @@ def gradient3d_section(dev, nt, every, order=8):
             "gradient_over_forward": round(tg / tf, 3), "misfit": mis}
 
 
-def salt3d_section(dev, nt, budget="40e9"):
+def salt3d_section(dev, nt, crop_nt=600, budget="40e9"):
     """3-D salt workload (512x512x256 model + 24-cell sponge, 560x560x304
     padded, 8th order, 512x512 receivers): the forward's rate, and the
     gradient with binomial (revolve) checkpointing under a snapshot budget,
@@ -269,7 +269,52 @@ def salt3d_section(dev, nt, budget="40e9"):
         torch.cuda.empty_cache()
     out["revolve"].update(slots=slots, snapshot_bytes=slots * slot_bytes,
                           forward_steps=fwd_steps, adjoint_steps=nt)
+    del v, v0, obs
+    torch.cuda.empty_cache()
+    # the 64^3 crop the oracle can run, timed beside the oracle's gradient
+    C = salt_crop(crop_nt)
+    vc, wc = t(C.v, torch.float32), t(C.wavelet, torch.float32)
+    sc, rc = t(C.src_pos, torch.int32), t(C.rec_pos, torch.int32)
+    cc = api.Config(dt=C.dt, dx=C.dx, order=C.order, nsponge=C.nb, eta_max=C.eta_max,
+                    ckpt="all")
+    oc = api.forward(vc, wc, sc, rc, cc)
+    vc0 = t(C.v_start, torch.float32)
+    api.gradient(vc0, oc, wc, sc, rc, cc)                           # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    api.gradient(vc0, oc, wc, sc, rc, cc)
+    torch.cuda.synchronize()
+    out["crop"] = {"workload": "64^3 crop of the salt model + 24-cell sponge (112^3 padded), "
+                               "%d steps, 64x64 receivers, all levels kept" % crop_nt,
+                   "gradient_s": round(time.perf_counter() - t0, 4)}
     return out
+
+
+_crop_cache = {}
+
+
+def salt_crop(nt):
+    """The 64^3 salt crop workload (built once per process: it cuts the full model)."""
+    from paper_1912_08063_amd import workloads as wl
+    if nt not in _crop_cache:
+        _crop_cache[nt] = wl.salt_3d_crop(nt=nt)
+    return _crop_cache[nt]
+
+
+def cpu_salt_crop(nt):
+    """The oracle's gradient on the 64^3 salt crop (its sponge included)."""
+    import numpy as np
+
+    import oracle
+    C = salt_crop(nt)
+    obs = np.zeros((1, C.nt, C.nrec))
+    t0 = time.perf_counter()
+    oracle.gradient(C.v_start, C.wavelet, C.src_pos, C.rec_pos, obs, C.dx, C.dt, C.order,
+                    C.nb, C.eta_max)
+    secs = time.perf_counter() - t0
+    return {"value": round(secs, 2), "unit": "s per %d-step gradient" % nt, "kind": "oracle",
+            "sample": "fp64 oracle gradient on the 64^3 salt crop (112^3 padded), all %d steps"
+                      % nt}
 
 
 def serve_section(nreq, scale, chunk):
@@ -323,7 +368,7 @@ def main():
                     help="gradient section: time only the batched call")
     ap.add_argument("--fwd16-nt", type=int, default=500)
     ap.add_argument("--cpu-grad3d-steps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--serve-scale", type=float, default=0.25)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device copy of GIB GiB (counter calibration)")
@@ -440,6 +485,9 @@ def main():
         if "gradient" in sections:
             log("cpu baseline: oracle 2-D gradient, one shot")
             out["cpu_baseline"]["gradient"] = cpu_gradient_2d(args.grad_nt)
+        if "salt3d" in sections:
+            log("cpu baseline: oracle gradient on the salt crop")
+            out["cpu_baseline"]["salt_crop"] = cpu_salt_crop(600)
         if "gradient3d" in sections:
             log("cpu baseline: oracle 3-D gradient sample")
             out["cpu_baseline"]["gradient3d"] = cpu_gradient_3d(args.cpu_grad3d_steps,
