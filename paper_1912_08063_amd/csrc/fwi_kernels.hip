@@ -25,6 +25,10 @@
 //    range of tiles: neighbouring tiles share their halos in the same L2.
 //  * Receiver sampling of level n is done by extra blocks of the launch that
 //    computes level n+1 (level n is read-only there), so it costs no launch.
+//  * Forward level L is field L mod R of the job's ring unless the launch's
+//    level map places it in a snapshot field: binomial checkpointing then
+//    reads restored states and writes snapshot states in place, without
+//    copies.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
