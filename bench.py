@@ -353,7 +353,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nt", type=int, default=2000)
-    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--cpu-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sections", default="forward,forward16,gradient,gradient3d,salt3d,serve",
                     help="comma list of: forward (headline), forward16 (16th order), gradient "

@@ -648,11 +648,23 @@ void rv_advance(Ctx &c, Held &h, int cur, int to, int shot, bool record)
     }
 }
 
-// Snapshot of levels t, t-1 into slot: copies what the steps did not write there.
+// Snapshot of levels t, t-1 into slot: copies what the steps did not write
+// there.  A source held in the other field of the same slot is copied first,
+// in a launch of its own.  (The binomial schedules never do this: a slot is
+// not overwritten one step after it was restored.)
 int rv_takeshot(Ctx &c, Held &h, int slot, int t)
 {
     const int mask = (h.field(t) != 2 * slot ? 1 : 0) | (h.field(t - 1) != 2 * slot + 1 ? 2 : 0);
-    if (mask) TRY(snapshot(c, slot, t, 0, mask, h.map({t, t - 1})));
+    const LevelMap m = h.map({t, t - 1});
+    if (mask == 3 && h.field(t - 1) == 2 * slot) {
+        TRY(snapshot(c, slot, t, 0, 2, m));
+        TRY(snapshot(c, slot, t, 0, 1, m));
+    } else if (mask == 3 && h.field(t) == 2 * slot + 1) {
+        TRY(snapshot(c, slot, t, 0, 1, m));
+        TRY(snapshot(c, slot, t, 0, 2, m));
+    } else if (mask) {
+        TRY(snapshot(c, slot, t, 0, mask, m));
+    }
     return FWI_OK;
 }
 
