@@ -970,9 +970,20 @@ void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st)
 // then the psi update): the fused kernel carries two 17-plane queues at 2
 // waves per SIMD, each pass one queue at 4 (300 vs 2 x ~115 us per step on a
 // 304^3 grid).  Both compute bitwise the same values.  At 8th order the fused
-// kernel is as fast as the two passes (207 vs 106 + 99 us) and stays.
+// kernel is as fast as the two passes (207 vs 106 + 99 us) and stays;
+// FWI_SPLIT_ADJ=1 selects the two passes there too.
 template <int M>
-constexpr bool kSplitAdjoint = M >= 8;
+static bool split_adjoint()
+{
+    if constexpr (M >= 8) {
+        return true;
+    } else if constexpr (M == 4) {
+        const char *e = getenv("FWI_SPLIT_ADJ");
+        return e && atoi(e) != 0;
+    } else {
+        return false;
+    }
+}
 
 template <int M, int NW, int RY>
 static void launch_3d(bool adj, const Job *jobs, const int *prefix, int njobs, int step,
@@ -982,16 +993,21 @@ static void launch_3d(bool adj, const Job *jobs, const int *prefix, int njobs, i
     if (!adj) {
         hipLaunchKernelGGL((k_step3d<M, kFwd, NW, RY>), g, b, 0, st, jobs, prefix, njobs, step,
                            ttiles, remap, lm);
-    } else if constexpr (kSplitAdjoint<M>) {
-        // the imaging pass reads psi^{k+1} and p^k, which the psi pass leaves intact
-        hipLaunchKernelGGL((k_step3d<M, kImage, NW, RY>), g, b, 0, st, jobs, prefix, njobs,
-                           step, ttiles, remap, lm);
-        hipLaunchKernelGGL((k_step3d<M, kAdjPsi, NW, RY>), g, b, 0, st, jobs, prefix, njobs,
-                           step, ttiles, remap, lm);
-    } else {
+        return;
+    }
+    if constexpr (M >= 4) {
+        if (split_adjoint<M>()) {
+            // the imaging pass reads psi^{k+1} and p^k, which the psi pass leaves intact
+            hipLaunchKernelGGL((k_step3d<M, kImage, NW, RY>), g, b, 0, st, jobs, prefix, njobs,
+                               step, ttiles, remap, lm);
+            hipLaunchKernelGGL((k_step3d<M, kAdjPsi, NW, RY>), g, b, 0, st, jobs, prefix, njobs,
+                               step, ttiles, remap, lm);
+            return;
+        }
+    }
+    if constexpr (M < 8)
         hipLaunchKernelGGL((k_step3d<M, kAdj, NW, RY>), g, b, 0, st, jobs, prefix, njobs, step,
                            ttiles, remap, lm);
-    }
 }
 
 template <int M, int NW, int RY>
@@ -999,16 +1015,20 @@ static hipError_t occupancy_3d(int *n, bool adj)
 {
     const int t = 64 * NW;
     if (!adj) return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_step3d<M, kFwd, NW, RY>, t, 0);
-    if constexpr (!kSplitAdjoint<M>) {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_step3d<M, kAdj, NW, RY>, t, 0);
-    } else {
-        int a = 0, c = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_step3d<M, kAdjPsi, NW, RY>, t, 0);
-        if (e == hipSuccess)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_step3d<M, kImage, NW, RY>, t, 0);
-        *n = a < c ? a : c;
-        return e;
+    if constexpr (M >= 4) {
+        if (split_adjoint<M>()) {
+            int a = 0, c = 0;
+            hipError_t e =
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_step3d<M, kAdjPsi, NW, RY>, t, 0);
+            if (e == hipSuccess)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_step3d<M, kImage, NW, RY>, t, 0);
+            *n = a < c ? a : c;
+            return e;
+        }
     }
+    if constexpr (M < 8)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, k_step3d<M, kAdj, NW, RY>, t, 0);
+    return hipErrorInvalidValue;
 }
 
 template <int M>

@@ -74,6 +74,20 @@ def test_3d_checkpoint_policies_bitwise_identical(order):
         assert np.array_equal(dv, ref), ck
 
 
+@pytest.mark.parametrize("shape", ["42", "4", "8"])
+def test_split_adjoint_equals_fused(shape, monkeypatch):
+    """At 8th order FWI_SPLIT_ADJ=1 runs the adjoint as a psi pass and an
+    imaging pass instead of the fused kernel: the same values bit for bit, for
+    every block shape of the adjoint launches."""
+    P, obs, v0 = _setup(wl.small_3d(shape=(30, 37, 100), nt=57, nshots=2, nrec=15))
+    monkeypatch.setenv("FWI_WAVES_ADJ", shape)
+    ref = gpu_gradient(P, v0, obs, "every:8")
+    monkeypatch.setenv("FWI_SPLIT_ADJ", "1")
+    got = gpu_gradient(P, v0, obs, "every:8")
+    assert got[0] == ref[0]
+    assert np.array_equal(got[1], ref[1])
+
+
 def test_revolve_without_copies_equals_copies(monkeypatch):
     """Binomial checkpointing reads restored states from their slots and
     writes snapshot states straight into them; FWI_REVOLVE_COPY=1 copies
