@@ -290,14 +290,15 @@ void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *
     *ntx = (g.nx + M + kTileX - 1) / kTileX;
     *nty = g.ndim == 3 ? (g.ny + ty - 1) / ty : 1;
     const int64_t per = (int64_t)(*ntx) * (*nty) * njobs;
-    // 3-D: as many z chunks as fill one wave of resident blocks of the forward
-    // step kernel (its occupancy times the CU count): fewer leave the memory
-    // system idle, more add z-chunk warm-up planes and a partial second wave.
-    // 2-D fields are small and largely cache-resident: many short chunks
-    // (16384 blocks: 12-row chunks for 32 shots of 1064 x 360, 8 % faster
-    // than 8192 on the 2-D gradient).
-    int64_t target = 16384;
+    int z;
     if (g.ndim == 3) {
+        // 3-D: the chunk count is chosen by how well the blocks fill whole
+        // waves of resident blocks (occupancy x CUs: a partial last wave idles
+        // part of the GPU) against the cost of short chunks (each warms its
+        // z-queue with 2M extra planes of the stencil field, one of the four
+        // streams).  Chunks are at least 4 planes long.  304^3 padded, 8th
+        // order: 8 chunks of 38 planes, 760 blocks for 768 slots; 560 x 560 x
+        // 304: 7 chunks of 44, 2205 blocks (3 % faster than 2 chunks of 152).
         static int cus = 0;
         if (cus == 0) {
             int dev = 0;
@@ -307,15 +308,33 @@ void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *
             if (cus <= 0) cus = 256;
         }
         const int occ = std::max(1, step_blocks_per_cu(3, g.M, code, adj));
-        target = (int64_t)occ * cus;
+        int64_t slots = (int64_t)occ * cus;
+        if (const char *e = getenv("FWI_TARGET_BLOCKS")) slots = std::max(1, atoi(e));
+        double best = 0.0;
+        z = g.nz;
+        for (int n = 1; n <= std::max(1, g.nz / 4); ++n) {
+            const int zc = (g.nz + n - 1) / n;
+            const int nc = (g.nz + zc - 1) / zc;
+            const double waves = (double)(per * nc) / (double)slots;
+            const double fill = waves / std::ceil(waves);
+            const double score = (1.0 + 0.5 * M / zc) / fill;
+            if (n == 1 || score < best - 1e-12) {
+                best = score;
+                z = zc;
+            }
+        }
+    } else {
+        // 2-D fields are small and largely cache-resident: many short chunks
+        // (16384 blocks: 12-row chunks for 32 shots of 1064 x 360, 8 % faster
+        // than 8192 on the 2-D gradient)
+        int64_t target = 16384;
+        if (const char *e = getenv("FWI_TARGET_BLOCKS")) target = std::max(1, atoi(e));
+        const int want = (int)std::max<int64_t>(1, (target + per - 1) / per);
+        z = (g.nz + want - 1) / want;
     }
-    if (const char *e = getenv("FWI_TARGET_BLOCKS")) target = std::max(1, atoi(e));
-    int want = (int)std::max<int64_t>(1, g.ndim == 3 ? target / per : (target + per - 1) / per);
-    int z = (g.nz + want - 1) / want;
     // at least 4 planes per chunk: grids too small to fill the GPU are bound
     // by the serial plane loop of each block, and 4-plane chunks beat 8-plane
-    // ones there (one 1064 x 360 2-D shot: +29 %); large grids get longer
-    // chunks from the target above
+    // ones there (one 1064 x 360 2-D shot: +29 %)
     z = std::max(z, std::min(g.nz, 4));
     if (const char *e = getenv("FWI_ZCHUNK")) z = std::max(1, atoi(e));
     z = std::min(z, g.nz);
