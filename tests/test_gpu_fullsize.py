@@ -5,10 +5,13 @@
   bench.py times (marked slow), element by element against the FP64 oracle.
 * 3-D forward workload (256^3 + sponge): the full grid and receiver plane
   against the oracle over the first 100 steps, and the whole 2000-step run
-  that bench.py times (marked slow: about two minutes of the oracle).
+  that bench.py times (marked slow: about two minutes of the oracle).  The
+  same grid at 16th order (60 steps) and its gradient (20 steps, every-7
+  snapshots), in the launch shapes their benchmarks use.
 * 3-D revolve workload (512x512x256, 3000 steps, 40 GB snapshot budget): the
   revolve gradient equals the every-50 gradient bitwise at full size (a
   property that holds at any size: both recompute the same forward levels),
+  the full grid's first 30 steps match the oracle,
   and the 64^3 crop run's gradient matches the oracle (600 steps, so that the
   oracle finishes in seconds).
 """
@@ -77,6 +80,41 @@ def test_layered_3d_headline_run_full_length():
     P = f32(wl.layered_3d(nt=2000))
     g = gpu_forward(P)
     o = oracle_forward(P)
+    assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
+
+
+def test_layered_3d_16th_order_full_grid_first_60_steps():
+    """The 16th-order forward benchmark's grid and launch shape (304^3 padded,
+    4 x 2 blocks) against the oracle over its first 60 steps."""
+    P = f32(wl.layered_3d(nt=60, order=16))
+    g = gpu_forward(P)
+    o = oracle_forward(P)
+    assert np.abs(o).max() > 0
+    assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
+
+
+def test_layered_3d_gradient_full_grid_20_steps():
+    """The 3-D gradient benchmark's grid and launch shapes (forward, recompute
+    and the fused adjoint on 304^3 padded cells) against the oracle.  20 steps
+    keep the oracle's stored states (all levels, fp64) near 5 GB; every-7
+    snapshots exercise the restore and recompute between them."""
+    P = f32(wl.layered_3d(nt=20))
+    obs = np.asarray(oracle_forward(P), np.float32).astype(np.float64)
+    v0 = np.asarray(0.98 * P.v, np.float32).astype(np.float64)
+    mis_g, dv_g, _ = gpu_gradient(P, v0, obs, "every:7")
+    mis_o, dv_o = oracle_gradient(P, v0, obs)
+    assert abs(mis_g - mis_o) <= 1e-3 * mis_o, (mis_g, mis_o)
+    assert rel_l2(dv_g, dv_o) <= 1e-3, rel_l2(dv_g, dv_o)
+
+
+def test_salt_3d_full_grid_first_30_steps():
+    """The salt benchmark's grid and launch shape (560 x 560 x 304 padded, 2205
+    forward blocks in 7 z-chunks) against the oracle over its first 30 steps,
+    every trace of the 512 x 512 receiver plane."""
+    P = f32(wl.salt_3d(nt=30))
+    g = gpu_forward(P)
+    o = oracle_forward(P)
+    assert np.abs(o).max() > 0
     assert rel_l2(g, o) <= 1e-4, rel_l2(g, o)
 
 
