@@ -61,6 +61,13 @@ struct Job {
     const int64_t *rec_off;    // [nrec] field offsets of the receiver cells
     const int32_t *rec_next;   // [nrec] next receiver on the same cell, -1 at the end
     const int32_t *rec_head;   // [nrec] 1 for the first receiver of its cell
+    // 2-D adjoint source: the first receiver of each receiver cell, grouped
+    // by the adjoint tile that holds the cell and sorted by row within it;
+    // tile t (local index) owns entries rt_start[t] .. rt_start[t+1]-1 of
+    // rt_rec (receiver) and rt_key (row << 6 | column within the tile)
+    const int32_t *rt_start;   // [adjoint tiles + 1] (2-D jobs only)
+    const int32_t *rt_rec;     // [receiver cells]
+    const int32_t *rt_key;     // [receiver cells]
     float *traces;         // [nt][nrec]
     const float *res;      // [nt][nrec] adjoint source
 };

@@ -121,6 +121,18 @@ __device__ __forceinline__ void gather_block(const Job *__restrict__ J, const Le
     J->traces[(int64_t)(n - 1) * J->nrec + r] = cur[J->rec_off[r]];
 }
 
+// Adjoint source at receiver r (the first of its cell): the sum of
+// res[k-1] over the receivers sharing the cell, in index order, so the
+// result is deterministic.  psi'^k gains kappa' times it (alpha = 1 on the
+// model grid, where every receiver sits).
+__device__ __forceinline__ float adj_source(const Job *__restrict__ J, int k, int r)
+{
+    const float *res = J->res + (int64_t)(k - 1) * J->nrec;
+    float s = res[r];
+    for (int q = J->rec_next[r]; q >= 0; q = J->rec_next[q]) s += res[q];
+    return s;
+}
+
 // Sponge factors from the squared depth d2 = sum_a d_a^2 into the sponge:
 // eta dt = eta_dt * d2, alpha = 1/(1 + eta dt), beta = (1 - eta dt) alpha.
 // out = alpha * val - beta * prev, written as alpha * (val - (1 - e) prev).
@@ -573,6 +585,7 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
     constexpr int KD = kDiffRadii < M ? kDiffRadii : M;   // radii in difference form
     __shared__ float sp[2 * LX];
     __shared__ float sf[ADJ ? 2 * LX : 1];
+    __shared__ float sinj[ADJ ? TX : 1];   // adjoint source of the current row
 
     const int lane = threadIdx.x;
     int b = blockIdx.x;
@@ -597,6 +610,13 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
     const int tx = local % T.ntx;
     const int tz = local / T.ntx;
     const int z0 = tz * T.zc, z1 = min(z0 + T.zc, nz);
+    // adjoint: the psi update adds the adjoint source at this tile's receiver
+    // cells (a list sorted by row; at most one cell per column)
+    int rp = 0, re = 0;
+    if constexpr (ADJ) {
+        rp = J->rt_start[local];
+        re = J->rt_start[local + 1];
+    }
 
     const gfloat *cur, *prv;
     gfloat *out;
@@ -692,7 +712,24 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
             if (src_here && z == J->src_z) val += srcv;
             const int dz = sponge_depth(z, nz, nb);
             const int64_t rz = (int64_t)(z + M) * p64 + col;
-            if (act) out[rz] = leapfrog(val, pv, dxs * dxs + dz * dz, eta_dt);
+            float o = leapfrog(val, pv, dxs * dxs + dz * dz, eta_dt);
+            if constexpr (ADJ) {
+                // receivers on row z: lane i takes the list's i-th, and the sum
+                // reaches the lane of its column through LDS
+                if (rp < re && (J->rt_key[rp] >> 6) == z) {
+                    const int idx = rp + lane;
+                    const int key = idx < re ? J->rt_key[idx] : -1;
+                    const int r = key >= 0 && (key >> 6) == z ? J->rt_rec[idx] : -1;
+                    sinj[lane] = 0.f;
+                    __syncthreads();
+                    if (r >= 0) sinj[key & 63] = adj_source(J, n, r);
+                    __syncthreads();
+                    if (act) o += kv * sinj[lane];
+                    rp += __popcll(__ballot(r >= 0));
+                    __syncthreads();
+                }
+            }
+            if (act) out[rz] = o;
             if constexpr (ADJ) {
                 if (accum) {
                     const float *LF = sf + (z & 1) * LX;
@@ -800,9 +837,8 @@ __global__ void k_gather(const Job *__restrict__ jobs, const int *__restrict__ g
     gather_block(J, lm, (blockIdx.x - gprefix[j]) * blockDim.x + threadIdx.x, J->n0 + step);
 }
 
-// Adjoint source: psi'^k[rec] += kappa'[rec] * res[k-1][rec] (alpha = 1 on the
-// model grid, where every receiver sits).  Receivers sharing a cell are summed
-// by the first of them, in index order, so the result is deterministic.
+// Adjoint source of 3-D steps, a launch after each adjoint step: psi'^k[rec]
+// += kappa'[rec] * res[k-1][rec] (2-D steps add it themselves).
 __global__ void k_adj_inject(const Job *__restrict__ jobs, const int *__restrict__ gprefix,
                              int njobs, int step)
 {
@@ -811,9 +847,7 @@ __global__ void k_adj_inject(const Job *__restrict__ jobs, const int *__restrict
     const int k = J->k0 - step;
     const int r = (blockIdx.x - gprefix[j]) * blockDim.x + threadIdx.x;
     if (k < J->adj_lo || k >= J->adj_hi || r >= J->nrec || !J->rec_head[r]) return;
-    const float *res = J->res + (int64_t)(k - 1) * J->nrec;
-    float s = res[r];
-    for (int q = J->rec_next[r]; q >= 0; q = J->rec_next[q]) s += res[q];
+    const float s = adj_source(J, k, r);
     const int64_t off = J->rec_off[r];
     float *psi = J->adj + (int64_t)(k & 1) * J->fstride;
     psi[off] += J->kappa[off] * s;

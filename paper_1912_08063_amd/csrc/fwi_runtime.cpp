@@ -201,10 +201,19 @@ int make_policy(const fwi_problem *p, const Geometry &g, int mode, const fwi_ckp
     }
 }
 
+// Upper bound on the tiles of one 2-D adjoint launch per shot (chunks are at
+// least one row): sizes the per-tile receiver lists before the tiling is
+// chosen.
+uint64_t max_adj_tiles_2d(const Geometry &g)
+{
+    return (uint64_t)((g.nx + g.M + kTileX - 1) / kTileX) * (uint64_t)g.nz;
+}
+
 // Byte layout of the workspace (ws) and of the checkpoint buffer (ck).
 struct Layout {
     uint64_t kappa = 0, ring = 0, adj = 0, grad = 0, snap = 0;
-    uint64_t jobs = 0, prefix = 0, rec_off = 0, rec_next = 0, rec_head = 0;
+    uint64_t jobs = 0, prefix = 0, rec_off = 0, rec_next = 0, rec_head = 0, rt_start = 0, rt_rec = 0;
+    uint64_t rt_key = 0;
     uint64_t res = 0, partial = 0, misfit = 0, fold1 = 0, fold2 = 0, vstats = 0;
     bool ring_in_ws = false, has_adj = false, has_res = false, has_fold = false;
     uint64_t ws_total = 0, ck_total = 0;
@@ -233,6 +242,11 @@ void make_layout(const fwi_problem *p, const Geometry &g, const Policy &po, int 
     L->rec_off = w.take(sizeof(int64_t) * S * R + 8);
     L->rec_next = w.take(sizeof(int32_t) * S * R + 4);
     L->rec_head = w.take(sizeof(int32_t) * S * R + 4);
+    if (g.ndim == 2) {
+        L->rt_start = w.take(sizeof(int32_t) * S * (max_adj_tiles_2d(g) + 1));
+        L->rt_rec = w.take(sizeof(int32_t) * S * R + 4);
+        L->rt_key = w.take(sizeof(int32_t) * S * R + 4);
+    }
     L->vstats = w.take(sizeof(float) * 3ull * vstats_blocks());
     if (mode == FWI_MODE_BACKWARD || mode == FWI_MODE_GRADIENT) {
         L->has_adj = true;
@@ -486,6 +500,40 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
     int64_t *d_roff = reinterpret_cast<int64_t *>(c.ws + c.L.rec_off);
     int32_t *d_rnext = reinterpret_cast<int32_t *>(c.ws + c.L.rec_next);
     int32_t *d_rhead = reinterpret_cast<int32_t *>(c.ws + c.L.rec_head);
+    // 2-D adjoint source lists: each receiver cell (its first receiver) under
+    // the adjoint tile that stores it, sorted by tile and then by row
+    const bool lists = D == 2;
+    const uint64_t mt = lists ? max_adj_tiles_2d(g) + 1 : 0;
+    int32_t *d_rtstart = lists ? reinterpret_cast<int32_t *>(c.ws + c.L.rt_start) : nullptr;
+    int32_t *d_rtrec = lists ? reinterpret_cast<int32_t *>(c.ws + c.L.rt_rec) : nullptr;
+    int32_t *d_rtkey = lists ? reinterpret_cast<int32_t *>(c.ws + c.L.rt_key) : nullptr;
+    std::vector<int32_t> rtstart((size_t)S * mt, 0), rtrec(lists ? (size_t)S * R : 0);
+    std::vector<int32_t> rtkey(rtrec.size());
+    if (lists) {
+        const Job::Tiling &T = til[1];
+        std::vector<std::pair<int64_t, int32_t>> key;
+        for (int s = 0; s < S; ++s) {
+            key.clear();
+            for (int r = 0; r < R; ++r) {
+                if (!rhead[(size_t)s * R + r]) continue;
+                const int64_t off = roff[(size_t)s * R + r];
+                const int zr = (int)(off / g.pitch) - g.M, cr = (int)(off % g.pitch);
+                const int64_t tile = (int64_t)(zr / T.zc) * T.ntx + cr / kTileX;
+                key.push_back({(tile * (int64_t)(g.nz + 1) + zr) * kTileX + cr % kTileX, r});
+            }
+            std::stable_sort(key.begin(), key.end());
+            int32_t *st = &rtstart[(size_t)s * mt];
+            int32_t *lst = &rtrec[(size_t)s * R];
+            int32_t *kk = &rtkey[(size_t)s * R];
+            for (size_t i = 0; i < key.size(); ++i) {
+                const int64_t tz = key[i].first / kTileX;   // tile * (nz + 1) + row
+                lst[i] = key[i].second;
+                kk[i] = (int32_t)((tz % (g.nz + 1)) << 6 | (key[i].first % kTileX));
+                st[tz / (g.nz + 1) + 1] += 1;
+            }
+            for (uint64_t t = 1; t < mt; ++t) st[t] += st[t - 1];
+        }
+    }
     double cell = 1.0;
     for (int a = 0; a < D; ++a) cell *= p->dx;
     c.jobs.assign(S, Job{});
@@ -521,6 +569,9 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
         J.rec_off = d_roff + (size_t)s * R;
         J.rec_next = d_rnext + (size_t)s * R;
         J.rec_head = d_rhead + (size_t)s * R;
+        J.rt_start = lists ? d_rtstart + (size_t)s * mt : nullptr;
+        J.rt_rec = lists ? d_rtrec + (size_t)s * R : nullptr;
+        J.rt_key = lists ? d_rtkey + (size_t)s * R : nullptr;
         J.traces = traces ? traces + (size_t)s * p->nt * R : nullptr;
         J.res = res ? res + (size_t)s * p->nt * R : nullptr;
         prefix[s + 1] = prefix[s] + J.tile[0].ntiles;
@@ -535,6 +586,16 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
     HIP_TRY(hipMemcpyAsync(c.d_jobs, c.jobs.data(), sizeof(Job) * S, hipMemcpyHostToDevice, c.st));
     HIP_TRY(hipMemcpyAsync(c.d_prefix, prefix.data(), sizeof(int) * prefix.size(),
                            hipMemcpyHostToDevice, c.st));
+    if (lists) {
+        HIP_TRY(hipMemcpyAsync(d_rtstart, rtstart.data(), rtstart.size() * 4,
+                               hipMemcpyHostToDevice, c.st));
+        if (R > 0) {
+            HIP_TRY(hipMemcpyAsync(d_rtrec, rtrec.data(), rtrec.size() * 4,
+                                   hipMemcpyHostToDevice, c.st));
+            HIP_TRY(hipMemcpyAsync(d_rtkey, rtkey.data(), rtkey.size() * 4,
+                                   hipMemcpyHostToDevice, c.st));
+        }
+    }
     if (R > 0) {
         HIP_TRY(hipMemcpyAsync(d_roff, roff.data(), roff.size() * 8, hipMemcpyHostToDevice, c.st));
         HIP_TRY(hipMemcpyAsync(d_rnext, rnext.data(), rnext.size() * 4, hipMemcpyHostToDevice, c.st));
@@ -567,8 +628,9 @@ int adj_step(Ctx &c, int k, const LevelMap &lm = LevelMap{})
 {
     launch_step(c.g.ndim, c.g.M, c.nw_adj, true, c.d_jobs, c.d_prefix + 2 * (c.p->nshots + 1),
                 c.p->nshots, -k, c.atiles, 0, c.remap, lm, c.st);
-    launch_adj_inject(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
-                      c.gthreads, -k, c.st);
+    if (c.g.ndim == 3)   // 2-D adjoint steps add the adjoint source themselves
+        launch_adj_inject(c.d_jobs, c.d_prefix + c.p->nshots + 1, c.p->nshots, c.gblocks,
+                          c.gthreads, -k, c.st);
     return FWI_OK;
 }
 
@@ -1304,7 +1366,7 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
                 const int ttiles = g.tp.back(), gblocks = g.gp.back();
                 launch_step(g.ndim, g.M, g.nw, g.adj != 0, g.d_jobs, g.d_prefix, n, j, ttiles,
                             g.adj ? 0 : gblocks, 1, LevelMap{}, st);
-                if (g.adj)
+                if (g.adj && g.ndim == 3)   // 2-D steps add the adjoint source themselves
                     launch_adj_inject(g.d_jobs, g.d_prefix + n + 1, n, gblocks, g.gthreads, j, st);
             }
         }
