@@ -8,7 +8,9 @@
 // fp32 accuracy, the outer radii as plain sums) and kappa' = (v dt / dx)^2.  The adjoint launch applies the same operator to
 // the scaled adjoint field psi' (psi = kappa*alpha*lambda, divided by dx^2),
 // for which the discrete adjoint recurrence IS the forward recurrence, and
-// accumulates the imaging condition g += psi'^{k+1} * L'p^k.
+// accumulates the imaging condition g += psi'^{k+1} * L'p^k.  The adjoint
+// source enters at the receiver cells: inside the step in 2-D, by a launch
+// after each step in 3-D.
 //
 // Design for CDNA4 (the paper's MXU band-matrix formulation does not apply:
 // the star stencil is banded, not a dense contraction, and the step is HBM
