@@ -37,6 +37,22 @@ def test_gradient_2d(order):
     _check(P, obs, v0, "every:25")
 
 
+def test_gradient_2d_receivers_on_tile_and_chunk_edges(monkeypatch):
+    """2-D adjoint steps add the adjoint source themselves, per tile and row:
+    a full receiver row (64 cells per tile), cells on both sides of tile and
+    row-chunk edges, and a duplicated cell, for two shots.  With nb = 6 and
+    an M = 4 frame, model column c is memory column c + 10 (tiles start at
+    multiples of 64) and model row r is padded row r + 6 (chunks of 10 rows)."""
+    monkeypatch.setenv("FWI_ZCHUNK", "10")
+    P = wl.small_2d(nz=40, nx=150, nt=120, nb=6, nshots=2, nrec=156)
+    rec = [[4, x] for x in range(150)] + [[3, 53], [3, 54], [13, 117], [14, 118], [39, 149],
+                                          [3, 53]]
+    P.rec_pos[:] = np.array(rec, dtype=np.int32)
+    P.src_pos[:] = [[20, 75], [5, 10]]
+    P, obs, v0 = _setup(P)
+    _check(P, obs, v0, "every:10")
+
+
 @pytest.mark.parametrize("order", [8, 16])
 def test_gradient_3d(order):
     P, obs, v0 = _setup(wl.small_3d(shape=(26, 22, 75), nt=90, order=order, nshots=2, nrec=30),
