@@ -46,6 +46,17 @@ def recorded_traffic():
         return None
 
 
+def cpu_model():
+    """The host CPU's model name (Linux), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(P, nt_sample):
     """The oracle as it stands, on the same model for nt_sample steps."""
     import oracle
@@ -55,7 +66,7 @@ def cpu_baseline(P, nt_sample):
     secs = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": P.padded_cells * nt_sample / secs / 1e9, "unit": "Gcell-updates/s",
-            "cores": cores, "kind": "oracle",
+            "cores": cores, "cpu": cpu_model(), "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": "fp64 oracle forward on the same 304^3 padded grid, %d of %d time steps "
                       "(%.1f s, set-up included)" % (nt_sample, P.nt, secs)}
 
