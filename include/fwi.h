@@ -191,6 +191,28 @@ int fwi_velocity_range(const float *v, int64_t n, float *h_vmin, float *h_vmax, 
 int fwi_revolve_schedule(int32_t nsteps, int32_t slots, int32_t *h_actions, int64_t cap,
                          int64_t *h_count, int64_t *h_forward_steps);
 
+/*
+ * The launches a gradient with binomial checkpointing issues, for one shot
+ * of `nsteps` steps and `slots` snapshot slots, computed on the host without
+ * a device: the forward sweep and then the backward sweep, in order.  It
+ * exposes the placement of levels in the ring and in snapshot slots for
+ * verification.  Writes up to `cap` launches of ten int32 each into h_ops
+ * (may be NULL with cap 0) and their count into h_count:
+ *   {kind, a, b, c, lev0, fld0, lev1, fld1, lev2, fld2}
+ *   kind 1: forward step from level a (reads a and a-1, writes a+1);
+ *   kind 2: adjoint step at level a (reads forward level a);
+ *   kind 3: snapshot copy for slot a at time b; c & 3 is the direction (0:
+ *           levels b, b-1 into fields 2a, 2a+1; 1: fields into the ring; 2:
+ *           zero levels 0, -1 in the ring) and c >> 2 a mask (bit w: level
+ *           b - w).
+ * (lev_i, fld_i) are the launch's level map: level lev_i is read or written
+ * in snapshot field fld_i instead of the ring (lev_i = INT32_MIN: unused).
+ * Every other level L is ring entry L mod 2.  Errors: FWI_EINVAL for
+ * nsteps < 1, slots < 0 or NULL outputs.
+ */
+int fwi_revolve_plan(int32_t nsteps, int32_t slots, int32_t *h_ops, int64_t cap,
+                     int64_t *h_count);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of independent one-shot jobs.
  *

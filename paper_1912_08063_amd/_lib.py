@@ -20,7 +20,7 @@ OP_ADVANCE, OP_TAKESHOT, OP_RESTORE, OP_ADJOINT, OP_RESTART = 1, 2, 3, 4, 5
 
 EXPORTS = ["fwi_strerror", "fwi_last_error", "fwi_cfl_limit", "fwi_workspace_bytes",
            "fwi_forward", "fwi_gradient", "fwi_forward_ckpt", "fwi_backward",
-           "fwi_revolve_schedule", "fwi_velocity_range", "fwi_job_bytes", "fwi_job_create",
+           "fwi_revolve_schedule", "fwi_revolve_plan", "fwi_velocity_range", "fwi_job_bytes", "fwi_job_create",
            "fwi_jobs_ws_bytes", "fwi_jobs_advance", "fwi_job_query", "fwi_job_misfit",
            "fwi_job_destroy"]
 JOB_FORWARD, JOB_GRADIENT = 0, 1
@@ -73,6 +73,7 @@ def load():
     lib.fwi_forward_ckpt.argtypes = [prob, vp, vp, vp, vp, ck, vp, vp, u64, vp, u64, vp]
     lib.fwi_backward.argtypes = [prob, vp, vp, vp, vp, ck, vp, u64, vp, vp, vp, u64, vp]
     lib.fwi_revolve_schedule.argtypes = [i32, i32, P(i32), i64, P(i64), P(i64)]
+    lib.fwi_revolve_plan.argtypes = [i32, i32, P(i32), i64, P(i64)]
     lib.fwi_velocity_range.argtypes = [vp, i64, P(ctypes.c_float), P(ctypes.c_float), vp, u64,
                                        vp]
     lib.fwi_job_bytes.argtypes = [prob, i32, i32, P(u64)]
@@ -145,6 +146,23 @@ def fwi_backward(prob, v, src, src_pos, rec_pos, ckpt, ckpt_buf, ckpt_bytes, gra
     _check(load().fwi_backward(ctypes.byref(prob), v, src, src_pos, rec_pos,
                                ctypes.byref(ckpt), ckpt_buf, ckpt_bytes, grad_traces, dv, ws,
                                ws_bytes, stream), "fwi_backward")
+
+
+def fwi_revolve_plan(nsteps, slots):
+    """The launches of a binomial-checkpointing gradient (host only): a list of
+    (kind, a, b, c, level_map) with level_map {level: snapshot field}."""
+    lib = load()
+    count = ctypes.c_int64()
+    _check(lib.fwi_revolve_plan(nsteps, slots, None, 0, ctypes.byref(count)), "fwi_revolve_plan")
+    buf = (ctypes.c_int32 * (10 * max(count.value, 1)))()
+    _check(lib.fwi_revolve_plan(nsteps, slots, buf, count.value, ctypes.byref(count)),
+           "fwi_revolve_plan")
+    out = []
+    for i in range(count.value):
+        row = buf[10 * i:10 * i + 10]
+        lm = {row[4 + 2 * e]: row[5 + 2 * e] for e in range(3) if row[4 + 2 * e] != -2 ** 31}
+        out.append((row[0], row[1], row[2], row[3], lm))
+    return out
 
 
 def fwi_revolve_schedule(nsteps, slots, with_actions=True):

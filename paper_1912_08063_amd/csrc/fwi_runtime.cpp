@@ -377,6 +377,9 @@ struct Ctx {
     int remap = 1;
     int nw = 4, nw_adj = 42;
     std::vector<int> slot_time;
+    // plan mode (host only): launches are recorded here instead of issued,
+    // ten int32 per launch (see fwi_revolve_plan)
+    std::vector<int32_t> *plan = nullptr;
 
     float *f_at(uint64_t off, bool in_ws) const
     {
@@ -617,8 +620,16 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
     } while (0)
 
 // ------------------------------------------------------------ time loops
+void plan_op(Ctx &c, int kind, int a, int b, int d, const LevelMap &lm)
+{
+    const int32_t row[10] = {kind, a, b, d, lm.lev[0], lm.fld[0], lm.lev[1], lm.fld[1],
+                             lm.lev[2], lm.fld[2]};
+    c.plan->insert(c.plan->end(), row, row + 10);
+}
+
 int fwd_step(Ctx &c, int n, bool record, const LevelMap &lm = LevelMap{})
 {
+    if (c.plan) { plan_op(c, 1, n, 0, 0, lm); return FWI_OK; }
     launch_step(c.g.ndim, c.g.M, c.nw, false, c.d_jobs, c.d_prefix, c.p->nshots, n, c.ttiles,
                 record ? c.gblocks : 0, c.remap, lm, c.st);
     return FWI_OK;
@@ -626,6 +637,7 @@ int fwd_step(Ctx &c, int n, bool record, const LevelMap &lm = LevelMap{})
 
 int adj_step(Ctx &c, int k, const LevelMap &lm = LevelMap{})
 {
+    if (c.plan) { plan_op(c, 2, k, 0, 0, lm); return FWI_OK; }
     launch_step(c.g.ndim, c.g.M, c.nw_adj, true, c.d_jobs, c.d_prefix + 2 * (c.p->nshots + 1),
                 c.p->nshots, -k, c.atiles, 0, c.remap, lm, c.st);
     if (c.g.ndim == 3)   // 2-D adjoint steps add the adjoint source themselves
@@ -640,6 +652,7 @@ int snapshot(Ctx &c, int slot, int time, int dir, int mask = 3, const LevelMap &
 {
     if (dir != 2 && (slot < 0 || slot >= c.po.nsnap))
         return fail(FWI_EINVAL, "internal: snapshot slot %d of %d", slot, c.po.nsnap);
+    if (c.plan) { plan_op(c, 3, slot, time, dir | mask << 2, lm); return FWI_OK; }
     launch_snapshot(c.d_jobs, c.p->nshots, c.g.fstride, slot, time, dir, mask, lm, c.st);
     return FWI_OK;
 }
@@ -777,14 +790,14 @@ int forward_phase(Ctx &c, bool record)
 {
     const int nt = c.p->nt;
     const uint64_t fs = (uint64_t)c.g.fstride;
-    zero(c.jobs[0].ring, fs * c.po.R * c.p->nshots, c.st);
+    if (!c.plan) zero(c.jobs[0].ring, fs * c.po.R * c.p->nshots, c.st);
     if (c.po.kind == FWI_CKPT_REVOLVE) {
         int64_t steps = 0;
         std::vector<Action> acts = revolve_schedule(nt, c.po.nsnap, &steps);
         c.slot_time.assign(std::max(c.po.nsnap, 1), -1);
         // steps store only grid cells, so fields they write must start with
         // a zero frame: the snapshot store is cleared once
-        if (!revolve_copies() && c.po.nsnap > 0)
+        if (!revolve_copies() && c.po.nsnap > 0 && !c.plan)
             zero(c.jobs[0].snap, 2 * fs * c.po.nsnap * c.p->nshots, c.st);
         int cur = 0;
         Held h;
@@ -809,7 +822,7 @@ int forward_phase(Ctx &c, bool record)
                           c.gthreads, nt, h.map({nt}), c.st);
         TRY(rv_to_ring(c, h, nt));
         TRY(rv_to_ring(c, h, nt - 1));
-        HIP_TRY(hipGetLastError());
+        if (!c.plan) HIP_TRY(hipGetLastError());
         return FWI_OK;
     } else {
         const int K = c.po.every;
@@ -832,8 +845,10 @@ int backward_phase(Ctx &c)
 {
     const int nt = c.p->nt;
     const uint64_t fs = (uint64_t)c.g.fstride;
-    zero(c.jobs[0].adj, 2 * fs * c.p->nshots, c.st);
-    zero(c.jobs[0].grad, fs * c.p->nshots, c.st);
+    if (!c.plan) {
+        zero(c.jobs[0].adj, 2 * fs * c.p->nshots, c.st);
+        zero(c.jobs[0].grad, fs * c.p->nshots, c.st);
+    }
     adj_step(c, nt);
     if (c.po.kind == FWI_CKPT_REVOLVE) {
         int64_t steps = 0;
@@ -881,7 +896,7 @@ int backward_phase(Ctx &c)
             for (int k = base + K - 1; k >= std::max(base, 1); --k) adj_step(c, k);
         }
     }
-    HIP_TRY(hipGetLastError());
+    if (!c.plan) HIP_TRY(hipGetLastError());
     return FWI_OK;
 }
 
@@ -1198,6 +1213,35 @@ int fwi_revolve_schedule(int32_t nsteps, int32_t slots, int32_t *h_actions, int6
                 h_actions[2 * i] = acts[i].op;
                 h_actions[2 * i + 1] = acts[i].arg;
             }
+        return FWI_OK;
+    } catch (...) {
+        return fail(FWI_EINVAL, "internal error");
+    }
+}
+
+int fwi_revolve_plan(int32_t nsteps, int32_t slots, int32_t *h_ops, int64_t cap,
+                     int64_t *h_count)
+{
+    if (nsteps < 1 || slots < 0) return fail(FWI_EINVAL, "nsteps >= 1 and slots >= 0 required");
+    if (!h_count || (cap > 0 && !h_ops)) return fail(FWI_EINVAL, "NULL output");
+    try {
+        fwi_problem p{};
+        p.nt = nsteps;
+        p.nshots = 1;
+        Ctx c;
+        c.p = &p;
+        c.po.kind = FWI_CKPT_REVOLVE;
+        c.po.R = 2;
+        c.po.nsnap = std::min(slots, nsteps);
+        c.jobs.assign(1, Job{});
+        std::vector<int32_t> ops;
+        c.plan = &ops;
+        int st = forward_phase(c, false);
+        if (st) return st;
+        st = backward_phase(c);
+        if (st) return st;
+        *h_count = (int64_t)ops.size() / 10;
+        for (int64_t i = 0; i < cap * 10 && i < (int64_t)ops.size(); ++i) h_ops[i] = ops[i];
         return FWI_OK;
     } catch (...) {
         return fail(FWI_EINVAL, "internal error");

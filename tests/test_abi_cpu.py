@@ -95,6 +95,85 @@ def test_workspace_sizes_grow_with_the_policy():
     assert _lib.fwi_workspace_bytes(p, _lib.MODE_CKPT_BUF, ck_all) >= 301 * 4 * 4 * cells
 
 
+# ------------------------------------------------------ revolve placement
+def _replay_plan(nt, slots):
+    """Replays the library's binomial-checkpointing launches with labelled
+    fields: every field holds the time level it was last given.  Checks that
+    each forward step reads levels n and n-1 and each adjoint step level k,
+    that snapshot copies read the level they name, that no copy reads a field
+    the same launch overwrites, and that the adjoint visits nt .. 1 once
+    each."""
+    plan = _lib.fwi_revolve_plan(nt, slots)
+    ring = {0: 0, 1: -1}              # ring entry -> level (0 and -1: zero states)
+    snap = {}                          # snapshot field -> level
+    adj, fwd = [], 0
+    zero = lambda L: L <= 0
+
+    def get(L, lm):
+        return snap.get(lm[L]) if L in lm else ring.get(L % 2)
+
+    def same(have, L):
+        return have == L or (zero(L) and have is not None and zero(have))
+
+    for kind, a, b, c, lm in plan:
+        if kind == 1:
+            fwd += 1
+            for L in (a, a - 1):
+                assert same(get(L, lm), L), (nt, slots, "step", a, L, get(L, lm))
+            if a + 1 in lm:
+                snap[lm[a + 1]] = a + 1
+            else:
+                ring[(a + 1) % 2] = a + 1
+        elif kind == 2:
+            assert same(get(a, lm), a), (nt, slots, "adjoint", a, get(a, lm))
+            adj.append(a)
+        else:
+            d, mask = c & 3, c >> 2
+            ws = [w for w in (0, 1) if mask >> w & 1]
+            if d == 0:
+                dst = {2 * a + w for w in ws}
+                vals = {}
+                for w in ws:
+                    L = b - w
+                    assert not (L in lm and lm[L] in dst and lm[L] != 2 * a + w), (nt, slots, "race")
+                    assert same(get(L, lm), L), (nt, slots, "snapshot source", L)
+                    vals[w] = get(L, lm)
+                for w in ws:
+                    snap[2 * a + w] = vals[w]
+            elif d == 1:
+                for w in ws:
+                    ring[(b - w) % 2] = snap[2 * a + w]
+            else:
+                ring[0], ring[1] = 0, -1
+    assert adj == list(range(nt, 0, -1)), (nt, slots)
+    return fwd
+
+
+@pytest.mark.parametrize("slots", [0, 1, 2, 3, 5, 9, 48])
+def test_revolve_placement_replays(slots):
+    """The copy-free placement of levels in snapshot slots (restores read the
+    slot; the steps producing a snapshot write into it), replayed from the
+    library's own launch plan."""
+    for nt in list(range(1, 90)) + [250, 601]:
+        if slots > nt:
+            continue
+        fwd = _replay_plan(nt, slots)
+        assert fwd == _lib.fwi_revolve_schedule(nt, min(slots, nt), with_actions=False)[1], nt
+
+
+def test_revolve_placement_copies_only_where_needed():
+    """Under the salt workload's schedule (3000 steps, 48 slots): no restore
+    copies, no two-field snapshot copies; the only copies are the older level
+    of the 2465 snapshots taken one step after the previous one, plus the
+    two restarts' zero fills.  7675 forward and 3000 adjoint launches."""
+    from collections import Counter
+    plan = _lib.fwi_revolve_plan(3000, 48)
+    kinds = Counter(p[0] for p in plan)
+    assert kinds[1] == 7675 and kinds[2] == 3000
+    copies = Counter((c & 3, c >> 2) for kind, a, b, c, lm in plan if kind == 3)
+    assert copies == Counter({(0, 2): 2465, (2, 3): 2})
+
+
 # ------------------------------------------------------------------ revolve
 @functools.lru_cache(maxsize=None)
 def _dp(l, s):
