@@ -12,3 +12,31 @@ def test_more_than_one_gpu_exits_with_a_message():
     assert p.returncode == 2
     assert "one GPU" in p.stderr
     assert p.stdout == ""
+
+
+def test_recorded_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    """roofline.traffic comes from rocprofv3 counter runs recorded with the
+    SHA-1 of the kernel and runtime sources they measured: it is reported only
+    while both files are unchanged, and is null otherwise."""
+    import json
+    import shutil
+    sys.path.insert(0, ROOT)
+    import bench
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_k_step3d_fwd_layered304.json")))
+    assert bench.recorded_traffic() == rec["traffic_bytes_per_launch"]
+    assert rec["traffic_bytes_per_launch"] == (rec["fetch_bytes_per_launch"]
+                                               + rec["write_bytes_per_launch"])
+    # a copy of the tree with one source byte changed
+    fake = tmp_path / "repo"
+    os.makedirs(fake / "profiles")
+    shutil.copy(os.path.join(ROOT, "profiles", "traffic_k_step3d_fwd_layered304.json"),
+                fake / "profiles")
+    for src in rec["sources_sha1"]:
+        os.makedirs(fake / os.path.dirname(src), exist_ok=True)
+        shutil.copy(os.path.join(ROOT, src), fake / src)
+    monkeypatch.setattr(bench, "ROOT", str(fake))
+    assert bench.recorded_traffic() == rec["traffic_bytes_per_launch"]
+    first = next(iter(rec["sources_sha1"]))
+    with open(fake / first, "a") as f:
+        f.write("\n")
+    assert bench.recorded_traffic() is None
