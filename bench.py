@@ -71,6 +71,108 @@ def cpu_baseline(P, nt_sample):
                       "(%.1f s, set-up included)" % (nt_sample, P.nt, secs)}
 
 
+def fstride_of(P):
+    """Floats per field allocation of a 3-D problem (the library's layout: the
+    padded grid plus an M-cell zero frame, rows padded to 64 floats)."""
+    M = P.order // 2
+    nz, ny, nx = (n + 2 * P.nb for n in P.v.shape)
+    pitch = -(-(nx + 2 * M) // 64) * 64
+    return (nz + 2 * M) * (ny + 2 * M) * pitch
+
+
+def median_time(fn, reps, sync):
+    """Median wall-clock seconds of `reps` calls of fn, each synchronised."""
+    times = []
+    for _ in range(reps):
+        sync()
+        t0 = time.perf_counter()
+        fn()
+        sync()
+        times.append(time.perf_counter() - t0)
+    return sorted(times)[len(times) // 2]
+
+
+def stream_ceiling(dev, fstride, reps=50):
+    """The hand-written 3-read/1-write stream (fwi_stream_probe) over four
+    fields of the headline grid's size, rotated like the step's ring: the rate
+    any kernel that reads p, p_prev and kappa' and writes p_next can reach on
+    this GPU.  Every variant (load width, cache policy, grid) is timed with
+    HIP events; the best is reported."""
+    import torch
+    from paper_1912_08063_amd import _lib
+    st = torch.cuda.current_stream(dev)
+    bufs = [torch.zeros(fstride, dtype=torch.float32, device=dev) for _ in range(4)]
+    best = None
+    names = {0: "32-bit", 1: "64-bit", 2: "128-bit"}
+    for var in (0, 1, 2, 4, 5, 6, 8, 9, 10, 12, 13, 14):
+        k = [0]
+
+        def launch():
+            i = k[0]
+            k[0] += 1
+            a, b, c, o = bufs[i % 3], bufs[(i + 1) % 3], bufs[3], bufs[(i + 2) % 3]
+            _lib.fwi_stream_probe(a.data_ptr(), b.data_ptr(), c.data_ptr(), o.data_ptr(),
+                                  fstride, var, st.cuda_stream)
+        for _ in range(3):
+            launch()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            launch()
+        e1.record(st)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        gbs = 16.0 * fstride / (us * 1e-6) / 1e9
+        if best is None or gbs > best["GBps"]:
+            best = {"GBps": round(gbs, 1), "us_per_launch": round(us, 2),
+                    "variant": "%s loads%s%s" % (names[var & 3], ", non-temporal" if var & 4 else "",
+                                                 ", 2048-block grid" if var & 8 else "")}
+    del bufs
+    torch.cuda.empty_cache()
+    best["frac_of_peak"] = round(best["GBps"] / HBM_PEAK_GBS, 4)
+    return best
+
+
+def c1_section(dev, calls=11):
+    """The 2-D one-shot forward (128^2 Gaussian anomaly + 20-cell sponge,
+    168^2 padded, 500 steps, 128 receivers): latency of one fwi_forward call
+    (median of `calls`) and its Gcell-updates/s.  The grid is far too small to
+    fill the GPU, so this measures the launch-bound path, not HBM."""
+    import numpy as np
+    import torch
+
+    from paper_1912_08063_amd import api, workloads as wl
+    P = wl.anomaly_2d()
+    t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
+    v, w = t(P.v, torch.float32), t(P.wavelet, torch.float32)
+    s, r = t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
+    cfg = api.Config(dt=P.dt, dx=P.dx, order=P.order, nsponge=P.nb, eta_max=P.eta_max)
+    ws = api.Workspace()
+    tr = api.forward(v, w, s, r, cfg, workspace=ws)
+    secs = median_time(lambda: api.forward(v, w, s, r, cfg, workspace=ws, out=tr), calls,
+                       torch.cuda.synchronize)
+    log("2-D one-shot forward: %.3f ms per call" % (secs * 1e3))
+    return {"workload": "2-D acoustic forward, 128^2 Gaussian anomaly + 20-cell sponge "
+                        "(168^2 padded), 8th order, 500 steps, 128 receivers",
+            "latency_ms": round(secs * 1e3, 3), "us_per_step": round(secs * 1e6 / P.nt, 2),
+            "Gcell_updates_per_s": round(P.padded_cells * P.nt / secs / 1e9, 3),
+            "calls": calls}
+
+
+def cpu_c1():
+    """The oracle on the whole 2-D one-shot forward (all 500 steps)."""
+    import oracle
+    from paper_1912_08063_amd import workloads as wl
+    P = wl.anomaly_2d()
+    t0 = time.perf_counter()
+    oracle.forward(P.v, P.wavelet, P.src_pos, P.rec_pos, P.dx, P.dt, P.order, P.nb, P.eta_max)
+    secs = time.perf_counter() - t0
+    return {"value": round(secs * 1e3, 2), "unit": "ms per 500-step forward", "kind": "oracle",
+            "Gcell_updates_per_s": round(P.padded_cells * P.nt / secs / 1e9, 4),
+            "sample": "fp64 oracle forward of the whole 2-D one-shot workload"}
+
+
 def forward16_section(dev, nt):
     """The headline geometry at 16th order (M = 8, a 49-point star): the
     stencil step's rate and its HIP-event launch time."""
@@ -146,13 +248,17 @@ def cpu_gradient_3d(nt_sample, nt):
                       % (nt_sample // 2, nt_sample, secs[0], secs[1], nt)}
 
 
-def gradient_section(dev, nt, shots, every, plain=True):
-    """2-D FWI gradient, 1024x320 model, 32 shots.  Batched: one fwi_gradient call for all
-    shots (each launch covers every shot's tiles).  Plain: one call per shot."""
+def gradient_section(dev, nt, shots, every, plain=True, reps=5):
+    """2-D FWI gradient, 1024x320 model, 32 shots (median of `reps` runs each).
+    Batched: one fwi_gradient call for all shots (each launch covers every
+    shot's tiles).  Autograd: the same shots through FWIForward (forward with
+    checkpoints, then backward of the least-squares loss).  Plain: one
+    fwi_gradient call per shot."""
     import numpy as np
     import torch
 
     from paper_1912_08063_amd import api, workloads as wl
+    from paper_1912_08063_amd.autograd import FWIForward
     P = wl.shots_2d(nt=nt, nshots=shots)
     t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
     w, s, r = t(P.wavelet, torch.float32), t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
@@ -161,32 +267,41 @@ def gradient_section(dev, nt, shots, every, plain=True):
     obs = api.forward(t(P.v, torch.float32), w, s, r, cfg)          # untimed
     v0 = t(P.v_start, torch.float32)
     ws = api.Workspace()
+    sync = torch.cuda.synchronize
+    out_mis = []
     api.gradient(v0, obs, w, s, r, cfg, workspace=ws)               # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mis, dv = api.gradient(v0, obs, w, s, r, cfg, workspace=ws)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    log("gradient batched: %d shots in %.3f s" % (shots, tb))
+    tb = median_time(lambda: out_mis.append(api.gradient(v0, obs, w, s, r, cfg, workspace=ws)[0]),
+                     reps, sync)
+    log("gradient batched: %d shots in %.3f s (median of %d)" % (shots, tb, reps))
+
+    def autograd_step():
+        vt = v0.clone().requires_grad_(True)
+        tr = FWIForward.apply(vt, w, s, r, cfg)
+        ((tr - obs) ** 2).sum().backward()
+    autograd_step()                                                 # warm-up
+    ta = median_time(autograd_step, reps, sync)
+    log("gradient autograd: %d shots in %.3f s (median of %d)" % (shots, ta, reps))
     out = {"workload": "2-D FWI gradient, 1024x320 model + 20-cell sponge, %d shots, %d steps, "
                        "1024 receivers, every-%d checkpoints" % (shots, nt, every),
-           "batched_shots_per_s": round(shots / tb, 3), "misfit": mis}
+           "batched_shots_per_s": round(shots / tb, 3),
+           "autograd_shots_per_s": round(shots / ta, 3),
+           "misfit": out_mis[-1], "runs": reps}
     if not plain:
         return out
     ws1 = api.Workspace()
     api.gradient(v0, obs[:1], w[:1], s[:1], r[:1], cfg, workspace=ws1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(shots):
-        api.gradient(v0, obs[i:i + 1], w[i:i + 1], s[i:i + 1], r[i:i + 1], cfg, workspace=ws1)
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
+
+    def plain_run():
+        for i in range(shots):
+            api.gradient(v0, obs[i:i + 1], w[i:i + 1], s[i:i + 1], r[i:i + 1], cfg,
+                         workspace=ws1)
+    tp = median_time(plain_run, max(1, reps // 2 + 1), sync)
     log("gradient plain: %d shots in %.3f s" % (shots, tp))
     out.update(plain_shots_per_s=round(shots / tp, 3), speedup=round(tp / tb, 3))
     return out
 
 
-def gradient3d_section(dev, nt, every, order=8):
+def gradient3d_section(dev, nt, every, order=8, reps=5):
     """3-D gradient on the headline geometry (304^3 padded, 8th order) over nt
     steps with every-k checkpoints: forward, recompute of each segment,
     adjoint and imaging condition.  Reported against the forward alone."""
@@ -205,23 +320,19 @@ def gradient3d_section(dev, nt, every, order=8):
     ws, wf = api.Workspace(), api.Workspace()
     api.gradient(v0, obs, w, s, r, cfg, workspace=ws)               # warm-up
     api.forward(v0, w, s, r, cfg, workspace=wf)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mis, dv = api.gradient(v0, obs, w, s, r, cfg, workspace=ws)
-    torch.cuda.synchronize()
-    tg = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    api.forward(v0, w, s, r, cfg, workspace=wf)
-    torch.cuda.synchronize()
-    tf = time.perf_counter() - t0
-    log("3-D gradient: %.3f s (forward %.3f s)" % (tg, tf))
+    mis = []
+    sync = torch.cuda.synchronize
+    tg = median_time(lambda: mis.append(api.gradient(v0, obs, w, s, r, cfg, workspace=ws)[0]),
+                     reps, sync)
+    tf = median_time(lambda: api.forward(v0, w, s, r, cfg, workspace=wf), reps, sync)
+    log("3-D gradient: %.3f s (forward %.3f s), medians of %d" % (tg, tf, reps))
     return {"workload": "3-D FWI gradient, 256^3 model + 24-cell sponge (304^3 padded), "
                         "order %d, %d steps, every-%d checkpoints" % (order, nt, every),
             "gradient_s": round(tg, 4), "forward_s": round(tf, 4),
-            "gradient_over_forward": round(tg / tf, 3), "misfit": mis}
+            "gradient_over_forward": round(tg / tf, 3), "misfit": mis[-1], "runs": reps}
 
 
-def salt3d_section(dev, nt, crop_nt=600, budget="40e9"):
+def salt3d_section(dev, nt, crop_nt=600, budget="40e9", reps=5):
     """3-D salt workload (512x512x256 model + 24-cell sponge, 560x560x304
     padded, 8th order, 512x512 receivers): the forward's rate, and the
     gradient with binomial (revolve) checkpointing under a snapshot budget,
@@ -240,13 +351,10 @@ def salt3d_section(dev, nt, crop_nt=600, budget="40e9"):
                      ckpt="revolve:%s" % budget)
     obs = torch.empty((1, nt, P.nrec), dtype=torch.float32, device=dev)
     ws = api.Workspace()
+    sync = torch.cuda.synchronize
     api.forward(v, w, s, r, cfg, workspace=ws, out=obs)            # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    api.forward(v, w, s, r, cfg, workspace=ws, out=obs)            # also the observed data
-    torch.cuda.synchronize()
-    tf = time.perf_counter() - t0
-    log("salt forward: %d steps in %.3f s" % (nt, tf))
+    tf = median_time(lambda: api.forward(v, w, s, r, cfg, workspace=ws, out=obs), reps, sync)
+    log("salt forward: %d steps in %.3f s (median of %d)" % (nt, tf, reps))
     v0 = t(P.v_start, torch.float32)
     del ws
     out = {"workload": "3-D FWI, salt model 512x512x256 + 24-cell sponge (560x560x304 padded), "
@@ -267,16 +375,14 @@ def salt3d_section(dev, nt, crop_nt=600, budget="40e9"):
         cg = dataclasses.replace(cfg, ckpt=spec)
         wg = api.Workspace()
         api.gradient(v0, obs, w, s, r, cg, workspace=wg)           # warm-up (and sizing)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        mis, dv = api.gradient(v0, obs, w, s, r, cg, workspace=wg)
-        torch.cuda.synchronize()
-        tg = time.perf_counter() - t0
-        log("salt gradient %s: %.3f s" % (spec, tg))
+        mis = []
+        tg = median_time(lambda: mis.append(api.gradient(v0, obs, w, s, r, cg, workspace=wg)[0]),
+                         reps, sync)
+        log("salt gradient %s: %.3f s (median of %d)" % (spec, tg, reps))
         key = spec.split(":")[0]
         out[key] = {"gradient_s": round(tg, 4), "gradient_over_forward": round(tg / tf, 3),
-                    "misfit": mis}
-        del wg, dv
+                    "misfit": mis[-1], "runs": reps}
+        del wg
         torch.cuda.empty_cache()
     out["revolve"].update(slots=slots, snapshot_bytes=slots * slot_bytes,
                           forward_steps=fwd_steps, adjoint_steps=nt)
@@ -291,13 +397,10 @@ def salt3d_section(dev, nt, crop_nt=600, budget="40e9"):
     oc = api.forward(vc, wc, sc, rc, cc)
     vc0 = t(C.v_start, torch.float32)
     api.gradient(vc0, oc, wc, sc, rc, cc)                           # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    api.gradient(vc0, oc, wc, sc, rc, cc)
-    torch.cuda.synchronize()
+    tcrop = median_time(lambda: api.gradient(vc0, oc, wc, sc, rc, cc), reps, sync)
     out["crop"] = {"workload": "64^3 crop of the salt model + 24-cell sponge (112^3 padded), "
                                "%d steps, 64x64 receivers, all levels kept" % crop_nt,
-                   "gradient_s": round(time.perf_counter() - t0, 4)}
+                   "gradient_s": round(tcrop, 4), "runs": reps}
     return out
 
 
@@ -329,14 +432,17 @@ def cpu_salt_crop(nt):
 
 
 def serve_section(nreq, scale, chunk):
-    """Serving (reduced grid/step scale): Poisson stream of mixed 2-D/3-D forward and
-    gradient requests at 0.8x the saturated rate; continuous batching vs one
-    request at a time."""
+    """Serving: a Poisson stream of mixed 2-D/3-D forward and gradient
+    requests (grid edges and step counts times `scale` of the configured
+    stream) at 0.8x the saturated rate; continuous batching against one
+    request at a time on the same stream."""
     import numpy as np
 
     from paper_1912_08063_amd import serve
+    t0 = time.perf_counter()
     reqs = serve.make_stream(nreq, 1.0, seed=4, scale=scale)
     serve.attach_observed(reqs)
+    log("serving x%.2f: %d requests generated in %.1f s" % (scale, nreq, time.perf_counter() - t0))
     for r in reqs:
         r.arrival = 0.0
     _, sat = serve.Server(max_active=64, chunk=chunk).run(reqs, realtime=True)
@@ -345,13 +451,21 @@ def serve_section(nreq, scale, chunk):
     for r, a in zip(reqs, arr):
         r.arrival = float(a)
     _, b = serve.Server(max_active=64, chunk=chunk).run(reqs, realtime=True)
-    log("serving batched: p50 %.3f p99 %.3f s" % (b["p50_latency_s"], b["p99_latency_s"]))
+    log("serving x%.2f batched: p50 %.3f p99 %.3f s" % (scale, b["p50_latency_s"],
+                                                       b["p99_latency_s"]))
     _, p = serve.Server(max_active=1, chunk=chunk).run(reqs, realtime=True)
-    log("serving plain: p50 %.3f p99 %.3f s" % (p["p50_latency_s"], p["p99_latency_s"]))
-    keep = ("shots_per_s", "p50_latency_s", "p99_latency_s", "makespan_s")
-    return {"workload": "Poisson stream of %d requests (70%% forward / 30%% gradient; 2-D and "
-                        "3-D layered models), grid edges and step counts x%.2f of the full "
-                        "stream, arrival rate 0.8x saturated" % (nreq, scale),
+    log("serving x%.2f plain: p50 %.3f p99 %.3f s" % (scale, p["p50_latency_s"],
+                                                     p["p99_latency_s"]))
+    keep = ("shots_per_s", "p50_latency_s", "p99_latency_s", "mean_latency_s", "makespan_s",
+            "failed")
+    n3 = sum(r.problem.v.ndim == 3 for r in reqs)
+    ng = sum(r.kind == "gradient" for r in reqs)
+    return {"workload": "Poisson stream of %d requests (%d gradient, %d forward; %d 3-D, %d 2-D; "
+                        "layered models), grid edges and step counts x%.2f of the configured "
+                        "stream (2-D 256^2-2048^2, 3-D 128^3-384^3, 1000-4000 steps), arrival "
+                        "rate 0.8x saturated" % (nreq, ng, nreq - ng, n3, nreq - n3, scale),
+            "requests": nreq,
+            "p99_tail_samples": max(1, int(round(0.01 * nreq))),
             "rate_per_s": round(rate, 3),
             "saturated_shots_per_s": round(sat["shots_per_s"], 3),
             "batched": {k: round(b[k], 4) for k in keep},
@@ -366,10 +480,12 @@ def main():
     ap.add_argument("--nt", type=int, default=2000)
     ap.add_argument("--cpu-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sections", default="forward,forward16,gradient,gradient3d,salt3d,serve",
-                    help="comma list of: forward (headline), forward16 (16th order), gradient "
+    ap.add_argument("--sections",
+                    default="forward,ceiling,c1,forward16,gradient,gradient3d,salt3d,serve",
+                    help="comma list of: forward (headline), ceiling (3-read/1-write stream "
+                         "probe), c1 (2-D one-shot latency), forward16 (16th order), gradient "
                          "(2-D, 32 shots), gradient3d (headline geometry), salt3d (salt "
-                         "model, revolve), serve (request stream)")
+                         "model, revolve), serve (request streams)")
     ap.add_argument("--salt-nt", type=int, default=3000)
     ap.add_argument("--grad-nt", type=int, default=3000)
     ap.add_argument("--grad-shots", type=int, default=32)
@@ -379,8 +495,11 @@ def main():
                     help="gradient section: time only the batched call")
     ap.add_argument("--fwd16-nt", type=int, default=500)
     ap.add_argument("--cpu-grad3d-steps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=1000)
-    ap.add_argument("--serve-scale", type=float, default=0.25)
+    ap.add_argument("--serve-requests", type=int, default=80,
+                    help="requests of the full-size serving stream")
+    ap.add_argument("--serve-small-requests", type=int, default=400,
+                    help="requests of the serving stream at --serve-small-scale (0: skip)")
+    ap.add_argument("--serve-small-scale", type=float, default=0.25)
     ap.add_argument("--calibrate-copy", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device copy of GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -479,6 +598,13 @@ def main():
         },
     }
     sections = set(args.sections.split(","))
+    if "ceiling" in sections:
+        ceil = stream_ceiling(dev, fstride_of(P))
+        ceil["step_frac_of_ceiling"] = round(achieved / ceil["GBps"], 4)
+        out["roofline"]["stream_ceiling"] = ceil
+        log("stream ceiling: %.1f GB/s (%s)" % (ceil["GBps"], ceil["variant"]))
+    if "c1" in sections:
+        out["c1"] = c1_section(dev)
     if "gradient" in sections:
         out["gradient"] = gradient_section(dev, args.grad_nt, args.grad_shots, 50,
                                            plain=not args.no_grad_plain)
@@ -489,10 +615,16 @@ def main():
     if "salt3d" in sections:
         out["salt3d"] = salt3d_section(dev, args.salt_nt)
     if "serve" in sections:
-        out["serving"] = serve_section(args.serve_requests, args.serve_scale, 50)
+        out["serving"] = serve_section(args.serve_requests, 1.0, 50)
+        if args.serve_small_requests > 0:
+            out["serving_small"] = serve_section(args.serve_small_requests,
+                                                 args.serve_small_scale, 50)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, %d steps)" % args.cpu_steps)
         out["cpu_baseline"] = cpu_baseline(P, args.cpu_steps)
+        if "c1" in sections:
+            log("cpu baseline: oracle 2-D one-shot forward")
+            out["cpu_baseline"]["c1"] = cpu_c1()
         if "gradient" in sections:
             log("cpu baseline: oracle 2-D gradient, one shot")
             out["cpu_baseline"]["gradient"] = cpu_gradient_2d(args.grad_nt)

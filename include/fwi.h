@@ -31,10 +31,14 @@
  *     field at time (n+1) dt; the initial state is P^0 = P^{-1} = 0.
  *   - dv is d(phi)/d(v) on the model grid, summed over shots, with the sponge
  *     damping held fixed.  Outputs are overwritten, never accumulated.
- *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream) and
- *     runs asynchronously; results are valid once the stream is synchronised.
- *     A call first copies the (small) position arrays to the host and
- *     synchronises `stream` once, to validate them.
+ *   - Work is enqueued on `stream` (a hipStream_t, NULL = default stream);
+ *     results are valid once the stream is synchronised.  A propagating call
+ *     first copies the (small) position arrays to the host and measures the
+ *     velocity range with one reduction kernel into the workspace, then
+ *     synchronises `stream` to validate them; fwi_forward, fwi_forward_ckpt,
+ *     fwi_backward and fwi_gradient also synchronise it at the end, for the
+ *     non-finite check below.  The time loop itself runs without host
+ *     synchronisation.
  *   - Workspaces: the caller allocates `ws` (>= the size reported by
  *     fwi_workspace_bytes, 256-byte aligned) and keeps it alive until the
  *     stream has finished the call's work.  The library allocates no device
@@ -42,9 +46,14 @@
  *     independent.
  *
  * Errors: every entry point returns an int status (FWI_OK == 0, negative on
- * error).  All argument checks happen on the host before any kernel is
- * launched, and on error no output is written.  Asynchronous device faults
- * surface as FWI_EHIP on a later call.  No C++ exception crosses the ABI.
+ * error).  Shapes, sizes and pointers are checked on the host before any
+ * kernel is launched; positions, velocities and the stability limit right
+ * after the velocity-range kernel (which writes only the workspace) and
+ * before any step.  On those errors no output is written.  FWI_ENONFINITE is
+ * the exception: it is detected after the outputs were written (a non-finite
+ * last wavefield, misfit or gradient), and the outputs then hold whatever the
+ * run produced.  Asynchronous device faults surface as FWI_EHIP on a later
+ * call.  No C++ exception crosses the ABI.
  */
 #ifndef FWI_H
 #define FWI_H
@@ -63,7 +72,7 @@ enum fwi_status {
     FWI_EBOUNDS = -3,     /* a source or receiver position outside the model grid */
     FWI_ENOMEM = -4,      /* workspace (or checkpoint buffer) smaller than required */
     FWI_EHIP = -5,        /* a HIP runtime call failed (message: fwi_last_error) */
-    FWI_ENONFINITE = -6,  /* the wavefield became non-finite */
+    FWI_ENONFINITE = -6,  /* the last wavefield, the misfit or the gradient is not finite */
     FWI_EUNSUPPORTED = -7 /* valid request this build does not implement */
 };
 
@@ -81,6 +90,9 @@ enum fwi_ckpt_kind {
     FWI_CKPT_REVOLVE = 2  /* binomial (revolve) schedule over `slots` snapshots */
 };
 
+/* eta_max value that asks the library for the default sponge strength. */
+#define FWI_ETA_AUTO (-1.0f)
+
 /* One propagation problem: model grid, discretisation and acquisition size. */
 typedef struct fwi_problem {
     int32_t ndim;       /* 2 or 3 */
@@ -90,7 +102,9 @@ typedef struct fwi_problem {
     int32_t nt;         /* number of time steps, >= 1 */
     int32_t order;      /* spatial order 2M: 2, 4, 8 or 16 */
     int32_t nsponge;    /* sponge width nb in cells (>= 0), added on every face */
-    float eta_max;      /* peak sponge damping rate (1/s), >= 0 */
+    float eta_max;      /* peak sponge damping rate (1/s), finite; < 0 (FWI_ETA_AUTO):
+                           3 v_max ln(10^3) / (2 nsponge dx), v_max the model's largest
+                           velocity (a 10^-3 round-trip decay through the sponge) */
     int32_t nshots;     /* shots, >= 1 */
     int32_t nrec;       /* receivers per shot, >= 0 */
 } fwi_problem;
@@ -177,6 +191,20 @@ int fwi_backward(const fwi_problem *prob, const float *v, const float *src,
  */
 int fwi_velocity_range(const float *v, int64_t n, float *h_vmin, float *h_vmax, void *ws,
                        uint64_t ws_bytes, void *stream);
+
+/*
+ * Diagnostic bandwidth ceiling: out[i] = a[i] + b[i] * c[i] for i < n, a
+ * pointwise stream with the forward step's memory mix (three fields read,
+ * one written, each once), which bounds the rate any step kernel reading
+ * p^n, p^{n-1} and kappa and writing p^{n+1} can reach.  Not part of the
+ * method.  variant: bits 0-1 load width (0: 32-bit, 1: 64-bit, 2: 128-bit
+ * per lane), bit 2 non-temporal loads and stores, bit 3 a grid of at most
+ * 2048 blocks striding over the arrays (else one lane per vector).  n is a
+ * positive multiple of 4, arrays 16-byte aligned, out distinct from the
+ * inputs.  Asynchronous on `stream`.  FWI_EINVAL on a bad argument.
+ */
+int fwi_stream_probe(const float *a, const float *b, const float *c, float *out, int64_t n,
+                     int32_t variant, void *stream);
 
 /*
  * Binomial checkpointing schedule (revolve, Griewank & Walther) for

@@ -20,7 +20,7 @@ OP_ADVANCE, OP_TAKESHOT, OP_RESTORE, OP_ADJOINT, OP_RESTART = 1, 2, 3, 4, 5
 
 EXPORTS = ["fwi_strerror", "fwi_last_error", "fwi_cfl_limit", "fwi_workspace_bytes",
            "fwi_forward", "fwi_gradient", "fwi_forward_ckpt", "fwi_backward",
-           "fwi_revolve_schedule", "fwi_revolve_plan", "fwi_velocity_range", "fwi_job_bytes", "fwi_job_create",
+           "fwi_revolve_schedule", "fwi_revolve_plan", "fwi_velocity_range", "fwi_stream_probe", "fwi_job_bytes", "fwi_job_create",
            "fwi_jobs_ws_bytes", "fwi_jobs_advance", "fwi_job_query", "fwi_job_misfit",
            "fwi_job_destroy"]
 JOB_FORWARD, JOB_GRADIENT = 0, 1
@@ -76,6 +76,7 @@ def load():
     lib.fwi_revolve_plan.argtypes = [i32, i32, P(i32), i64, P(i64)]
     lib.fwi_velocity_range.argtypes = [vp, i64, P(ctypes.c_float), P(ctypes.c_float), vp, u64,
                                        vp]
+    lib.fwi_stream_probe.argtypes = [vp, vp, vp, vp, i64, i32, vp]
     lib.fwi_job_bytes.argtypes = [prob, i32, i32, P(u64)]
     lib.fwi_job_create.argtypes = [prob, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp,
                                    P(vp)]
@@ -186,6 +187,10 @@ def fwi_velocity_range(v, n, ws, ws_bytes, stream):
     _check(load().fwi_velocity_range(v, n, ctypes.byref(lo), ctypes.byref(hi), ws, ws_bytes,
                                      stream), "fwi_velocity_range")
     return lo.value, hi.value
+
+
+def fwi_stream_probe(a, b, c, out, n, variant, stream):
+    _check(load().fwi_stream_probe(a, b, c, out, n, variant, stream), "fwi_stream_probe")
 
 
 def fwi_job_bytes(prob, kind, chunk):

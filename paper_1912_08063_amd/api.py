@@ -38,7 +38,7 @@ class Config:
     dx: float
     order: int = 8
     nsponge: int = 20
-    eta_max: Optional[float] = None   # None: 3 vmax ln(1000) / (2 nsponge dx)
+    eta_max: Optional[float] = None   # None: the library's 3 vmax ln(1000) / (2 nsponge dx)
     ckpt: str = "every:50"            # "all", "every:K", "revolve:SLOTS", "revolve:BUDGETe9B"
 
 
@@ -125,10 +125,8 @@ def make_problem(v, nt, cfg: Config, nshots, nrec) -> _lib.FwiProblem:
         p.shape[i] = int(n)
     p.dx, p.dt, p.nt = float(cfg.dx), float(cfg.dt), int(nt)
     p.order, p.nsponge = int(cfg.order), int(cfg.nsponge)
-    eta = cfg.eta_max
-    if eta is None:
-        eta = default_eta_max(velocity_range(v)[1], cfg.nsponge, cfg.dx)
-    p.eta_max = float(eta)
+    # a negative eta_max asks the library for its default from the model's v_max
+    p.eta_max = -1.0 if cfg.eta_max is None else float(cfg.eta_max)
     p.nshots, p.nrec = int(nshots), int(nrec)
     return p
 

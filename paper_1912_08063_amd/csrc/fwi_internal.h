@@ -20,6 +20,14 @@ constexpr int kTileX = 64;   // memory columns per tile (one wavefront)
 // 3-D blocks hold 4 or 8 wavefronts of 64 lanes, each thread owning 2 or 4
 // consecutive y rows: a tile is 64 (x) by rows * wavefronts (y)
 constexpr int kGatherThreads = 256;
+// Tiling flags of 3-D step launches.  kTileZFast: the z chunk is the fastest
+// index of a tile number (the chunks of one column are consecutive blocks),
+// otherwise the slowest.  kTileZAlt: odd chunks march down (from their last
+// plane to their first), so two neighbouring chunks read the planes around
+// their common boundary at the same time, at the start or at the end of
+// both, instead of once at the start and once at the end.
+constexpr int32_t kTileZFast = 1;
+constexpr int32_t kTileZAlt = 2;
 
 struct Job {
     // geometry of the padded grid and its field layout
@@ -36,6 +44,7 @@ struct Job {
     struct Tiling {
         int32_t ntx, nty, nzc, zc;   // tiles in x and y, z chunks and chunk length
         int32_t ntiles;              // ntx * nty * nzc
+        int32_t flags;               // kTile* bits (3-D launches only)
     } tile[2];
     int32_t ngather;             // gather blocks (forward record)
     // time: forward n = n0 + step, adjoint k = k0 - step; a launch updates a

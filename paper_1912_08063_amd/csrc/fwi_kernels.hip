@@ -269,11 +269,22 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     const int64_t plane = J->plane, fstride = J->fstride;
     const Job::Tiling &T = J->tile[ADJ ? 1 : 0];
     int local = b - prefix[j];
-    const int tx = local % T.ntx;
-    local /= T.ntx;
-    const int ty = local % T.nty;
-    const int tz = local / T.nty;
+    int tx, ty, tz;
+    if (T.flags & kTileZFast) {
+        tz = local % T.nzc;
+        local /= T.nzc;
+        tx = local % T.ntx;
+        ty = local / T.ntx;
+    } else {
+        tx = local % T.ntx;
+        local /= T.ntx;
+        ty = local % T.nty;
+        tz = local / T.nty;
+    }
     const int z0 = tz * T.zc, z1 = min(z0 + T.zc, nz);
+    // marching direction: plane i of the chunk (i = 0 .. npl-1) is zs + dir * i
+    const int dir = (T.flags & kTileZAlt) && (tz & 1) ? -1 : 1;
+    const int zs = dir > 0 ? z0 : z1 - 1, npl = z1 - z0;
 
     // cur: the stencil field; prv and kap: the two pointwise streams; out.
     // Imaging mode: cur = p^k, prv = psi^{k+1}, kap = out = g.
@@ -359,15 +370,16 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         if (r >= 0 && r < RY) { src_row = r; srcv = J->src_scale * J->wavelet[n]; }
     }
 
-    // ---- prologue: queue slots 0..2M hold planes z0-M .. z0+M; plane z0 in LDS
+    // ---- prologue: queue slot s (0..2M) holds plane zs + dir (s - M); plane
+    // zs in LDS.  Memory plane index = grid plane + M (the frame).
     float q[RY][Q];
     float f[FUSED ? RY : 1][FUSED ? Q : 1];
     float hy[HQ ? NYH : 1][HQ ? Q : 1], hx[HQ ? NXH : 1][HQ ? Q : 1];
     if constexpr (HQ) {
-        // halo ring: slot s holds the halos of plane z0 - M + s (s = M+1 .. 2M now)
+        // halo ring: slot s holds the halos of plane zs + dir (s - M) (s = M+1 .. 2M now)
 #pragma unroll
         for (int s = M + 1; s < Q; ++s) {
-            const rsrc_t ph = plane_rsrc(cur, z0 + s, plane, pbytes);
+            const rsrc_t ph = plane_rsrc(cur, zs + dir * (s - M) + M, plane, pbytes);
 #pragma unroll
             for (int h = 0; h < NYH; ++h) hy[h][s] = ldb(ph, hyo[h]);
 #pragma unroll
@@ -376,8 +388,9 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     }
 #pragma unroll
     for (int s = 0; s < Q; ++s) {
-        const rsrc_t pc = plane_rsrc(cur, z0 + s, plane, pbytes);   // grid plane z0 - M + s
-        const rsrc_t pf = plane_rsrc(fwd, z0 + s, plane, pbytes);
+        const int zm = zs + dir * (s - M) + M;
+        const rsrc_t pc = plane_rsrc(cur, zm, plane, pbytes);
+        const rsrc_t pf = plane_rsrc(fwd, zm, plane, pbytes);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
             q[i][s] = ldb(pc, roff[i]);
@@ -386,18 +399,18 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     }
     float kv[RY], pv[RY], gv[FUSED ? RY : 1];
     {
-        const rsrc_t pk = plane_rsrc(kap, z0 + M, plane, pbytes);
-        const rsrc_t pp = plane_rsrc(prv, z0 + M, plane, pbytes);
+        const rsrc_t pk = plane_rsrc(kap, zs + M, plane, pbytes);
+        const rsrc_t pp = plane_rsrc(prv, zs + M, plane, pbytes);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
             kv[i] = ldb(pk, roff[i]);
             pv[i] = ldb(pp, roff[i]);
-            if constexpr (FUSED) gv[i] = accum ? ldb(plane_rsrc(grad, z0 + M, plane, pbytes), roff[i]) : 0.f;
+            if constexpr (FUSED) gv[i] = accum ? ldb(plane_rsrc(grad, zs + M, plane, pbytes), roff[i]) : 0.f;
         }
-        const rsrc_t pc = plane_rsrc(cur, z0 + M, plane, pbytes);
-        const rsrc_t pf = plane_rsrc(fwd, z0 + M, plane, pbytes);
-        float *L = sp + (z0 & 1) * LS;
-        float *LF = FUSED ? sf + (z0 & 1) * LS : nullptr;
+        const rsrc_t pc = plane_rsrc(cur, zs + M, plane, pbytes);
+        const rsrc_t pf = plane_rsrc(fwd, zs + M, plane, pbytes);
+        float *L = sp;           // LDS buffer i & 1 holds chunk plane i
+        float *LF = FUSED ? sf : nullptr;
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
             L[(M + wv * RY + i) * LX + M + lane] = q[i][M];
@@ -418,35 +431,38 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     }
     __syncthreads();
 
-    for (int zb = z0; zb < z1; zb += Q) {
+    for (int ib = 0; ib < npl; ib += Q) {
 #pragma unroll
         for (int k = 0; k < Q; ++k) {
-            const int z = zb + k;
-            if (z < z1) {
-            const bool more = z + 1 < z1;
-            // ---- prefetch plane z+1 (queue front z+1+M, kappa', previous level, halos)
+            const int ii = ib + k;
+            if (ii < npl) {
+            const int z = zs + dir * ii;   // grid plane computed now
+            const bool more = ii + 1 < npl;
+            // ---- prefetch the next plane z+dir (queue front z+dir(1+M), kappa',
+            // previous level, halos); memory plane = grid plane + M
             float nq[RY], nk[RY], np[RY], nhy[NYH], nhx[NXH];
             float nfq[FUSED ? RY : 1], ng[FUSED ? RY : 1], nfy[FUSED ? NYH : 1], nfx[FUSED ? NXH : 1];
+            const int zf = z + dir * (1 + M) + M, zn = z + dir + M;
             if (more) {
-                const rsrc_t pq = plane_rsrc(cur, z + 1 + 2 * M, plane, pbytes);
-                const rsrc_t pk = plane_rsrc(kap, z + 1 + M, plane, pbytes);
-                const rsrc_t pp = plane_rsrc(prv, z + 1 + M, plane, pbytes);
-                const rsrc_t ph = plane_rsrc(cur, z + 1 + M, plane, pbytes);
+                const rsrc_t pq = plane_rsrc(cur, zf, plane, pbytes);
+                const rsrc_t pk = plane_rsrc(kap, zn, plane, pbytes);
+                const rsrc_t pp = plane_rsrc(prv, zn, plane, pbytes);
+                const rsrc_t ph = plane_rsrc(cur, zn, plane, pbytes);
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
                     nq[i] = ldb(pq, roff[i]);
                     nk[i] = ldb_stream(pk, roff[i]);
                     np[i] = ldb_stream(pp, roff[i]);
                 }
-                const rsrc_t phq = HQ ? plane_rsrc(cur, z + 1 + 2 * M, plane, pbytes) : ph;
+                const rsrc_t phq = HQ ? pq : ph;
 #pragma unroll
                 for (int h = 0; h < NYH; ++h) nhy[h] = ldb(phq, hyo[h]);
 #pragma unroll
                 for (int h = 0; h < NXH; ++h) nhx[h] = ldb(phq, hxo[h]);
                 if constexpr (FUSED) {
-                    const rsrc_t fq = plane_rsrc(fwd, z + 1 + 2 * M, plane, pbytes);
-                    const rsrc_t fh = plane_rsrc(fwd, z + 1 + M, plane, pbytes);
-                    const rsrc_t pg = plane_rsrc(grad, z + 1 + M, plane, pbytes);
+                    const rsrc_t fq = plane_rsrc(fwd, zf, plane, pbytes);
+                    const rsrc_t fh = plane_rsrc(fwd, zn, plane, pbytes);
+                    const rsrc_t pg = plane_rsrc(grad, zn, plane, pbytes);
 #pragma unroll
                     for (int i = 0; i < RY; ++i) {
                         nfq[i] = ldb(fq, roff[i]);
@@ -458,9 +474,9 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                     for (int h = 0; h < NXH; ++h) nfx[h] = ldb(fh, hxo[h]);
                 }
             }
-            // ---- plane z
-            const float *L = sp + (z & 1) * LS;
-            const float *LF = FUSED ? sf + (z & 1) * LS : nullptr;
+            // ---- plane z (queue slot (k + M + m) % Q holds plane z + dir m)
+            const float *L = sp + (ii & 1) * LS;
+            const float *LF = FUSED ? sf + (ii & 1) * LS : nullptr;
             const rsrc_t po = plane_rsrc(out, z + M, plane, pbytes);
             const rsrc_t pg = plane_rsrc(grad, z + M, plane, pbytes);
             const int dz = sponge_depth(z, nz, nb);
@@ -528,13 +544,13 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                     }
                 }
             }
-            // ---- rotate to plane z+1 and stage it in the other LDS buffer
+            // ---- rotate to plane z+dir and stage it in the other LDS buffer
             if (more) {
-                float *Ln = sp + ((z + 1) & 1) * LS;
-                float *LFn = FUSED ? sf + ((z + 1) & 1) * LS : nullptr;
+                float *Ln = sp + ((ii + 1) & 1) * LS;
+                float *LFn = FUSED ? sf + ((ii + 1) & 1) * LS : nullptr;
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
-                    q[i][k] = nq[i];   // slot k held plane z - M
+                    q[i][k] = nq[i];   // slot k held plane z - dir M
                     kv[i] = nk[i];
                     pv[i] = np[i];
                     Ln[(M + wv * RY + i) * LX + M + lane] = q[i][(k + M + 1) % Q];
@@ -857,9 +873,11 @@ __global__ void k_adj_inject(const Job *__restrict__ jobs, const int *__restrict
 
 // Misfit (Eq. 1) and adjoint source: res = 2 (d - obs); per-block partial sums
 // of (d - obs)^2 in fp64, reduced in a fixed order (deterministic).
-__global__ __launch_bounds__(256) void k_misfit(const float *__restrict__ d,
-                                                const float *__restrict__ obs,
-                                                float *__restrict__ res, int64_t n,
+// d and res may be the same array (traces recorded into the residual
+// buffer): each element is read and then written by the same thread, and
+// neither pointer is declared restrict.
+__global__ __launch_bounds__(256) void k_misfit(const float *d, const float *__restrict__ obs,
+                                                float *res, int64_t n,
                                                 double *__restrict__ partial)
 {
     __shared__ double red[256];
@@ -994,8 +1012,112 @@ __global__ __launch_bounds__(256) void k_vstats(const float *__restrict__ v, int
     }
 }
 
+// --------------------------------------------------- bandwidth ceiling probe
+// A pointwise stream with the forward step's memory mix: three fields read,
+// one written (out = a + b * c), each field touched once per launch.  Any
+// step kernel that reads p, p_prev and kappa' and writes p_next moves at
+// least these bytes, so the probe's rate bounds the step's on this chip.
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+template <typename V, bool NT>
+__device__ __forceinline__ V ld_probe(const V *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <typename V, bool NT>
+__device__ __forceinline__ void st_probe(V *p, V v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <typename V, bool NT>
+__global__ __launch_bounds__(256) void k_stream3r1w(const V *__restrict__ a,
+                                                    const V *__restrict__ b,
+                                                    const V *__restrict__ c,
+                                                    V *__restrict__ o, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        const V x = ld_probe<V, NT>(a + i), y = ld_probe<V, NT>(b + i), z = ld_probe<V, NT>(c + i);
+        st_probe<V, NT>(o + i, x + y * z);
+    }
+}
+
+template <typename V, bool NT>
+static void launch_probe_t(const float *a, const float *b, const float *c, float *o, int64_t n,
+                           bool persistent, hipStream_t st)
+{
+    constexpr int W = sizeof(V) / sizeof(float);
+    const int64_t nv = n / W;
+    const int64_t full = (nv + 255) / 256;
+    const int grid = (int)(persistent ? std::min<int64_t>(full, 2048) : full);
+    hipLaunchKernelGGL((k_stream3r1w<V, NT>), dim3(grid), dim3(256), 0, st,
+                       reinterpret_cast<const V *>(a), reinterpret_cast<const V *>(b),
+                       reinterpret_cast<const V *>(c), reinterpret_cast<V *>(o), nv);
+}
+
+// variant: bits 0-1 load width (0: 32-bit, 1: 64-bit, 2: 128-bit), bit 2
+// non-temporal, bit 3 a grid of at most 2048 blocks striding over the fields
+// (otherwise one lane per vector).  n is a multiple of 4.
+void launch_stream_probe(const float *a, const float *b, const float *c, float *o, int64_t n,
+                         int variant, hipStream_t st)
+{
+    const bool nt = (variant >> 2) & 1, pers = (variant >> 3) & 1;
+    switch (variant & 3) {
+    case 0:
+        if (nt) launch_probe_t<float, true>(a, b, c, o, n, pers, st);
+        else launch_probe_t<float, false>(a, b, c, o, n, pers, st);
+        break;
+    case 1:
+        if (nt) launch_probe_t<vf2, true>(a, b, c, o, n, pers, st);
+        else launch_probe_t<vf2, false>(a, b, c, o, n, pers, st);
+        break;
+    default:
+        if (nt) launch_probe_t<vf4, true>(a, b, c, o, n, pers, st);
+        else launch_probe_t<vf4, false>(a, b, c, o, n, pers, st);
+        break;
+    }
+}
+
+// Non-finite cells of forward level L of every job (ring slot L mod R):
+// per-block counts, partial[0 .. gridDim.x), summed on the host.
+__global__ __launch_bounds__(256) void k_nonfinite_level(const Job *__restrict__ jobs, int njobs,
+                                                         int L, float *__restrict__ partial)
+{
+    __shared__ float red[256];
+    float bad = 0.f;
+    for (int j = 0; j < njobs; ++j) {
+        const Job *J = jobs + j;
+        const float4 *f =
+            reinterpret_cast<const float4 *>(J->ring + (int64_t)mod_pos(L, J->R) * J->fstride);
+        const int64_t n4 = J->fstride / 4;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const float4 a = f[i];
+            bad += (isfinite(a.x) ? 0.f : 1.f) + (isfinite(a.y) ? 0.f : 1.f) +
+                   (isfinite(a.z) ? 0.f : 1.f) + (isfinite(a.w) ? 0.f : 1.f);
+        }
+    }
+    red[threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // ---------------------------------------------------------------- launchers
 int vstats_blocks() { return 256; }
+
+void launch_nonfinite_level(const Job *jobs, int njobs, int L, float *partial, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_nonfinite_level, dim3(vstats_blocks()), dim3(256), 0, st, jobs, njobs,
+                       L, partial);
+}
 
 void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st)
 {

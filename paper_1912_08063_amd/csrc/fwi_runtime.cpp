@@ -45,6 +45,9 @@ void launch_fold(int ndim, const Job *jobs, int njobs, int M, int gy, int nz, in
 int vstats_blocks();
 int step_blocks_per_cu(int ndim, int M, int nw, bool adj);
 void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st);
+void launch_nonfinite_level(const Job *jobs, int njobs, int L, float *partial, hipStream_t st);
+void launch_stream_probe(const float *a, const float *b, const float *c, float *o, int64_t n,
+                         int variant, hipStream_t st);
 }  // namespace fwi
 
 using namespace fwi;
@@ -98,8 +101,8 @@ int check_problem(const fwi_problem *p)
     if (p->order != 2 && p->order != 4 && p->order != 8 && p->order != 16)
         return fail(FWI_EINVAL, "order must be 2, 4, 8 or 16");
     if (p->nsponge < 0 || p->nsponge > 4096) return fail(FWI_EINVAL, "nsponge out of range");
-    if (!(p->eta_max >= 0.f) || !std::isfinite(p->eta_max))
-        return fail(FWI_EINVAL, "eta_max must be finite and >= 0");
+    if (!std::isfinite(p->eta_max))
+        return fail(FWI_EINVAL, "eta_max must be finite (negative: derived from v_max)");
     if (p->nshots < 1) return fail(FWI_EINVAL, "nshots must be >= 1");
     if (p->nrec < 0) return fail(FWI_EINVAL, "nrec must be >= 0");
     return FWI_OK;
@@ -154,6 +157,15 @@ double max_symbol(int order)
         best = std::max(best, -s);
     }
     return best;
+}
+
+// Default peak damping of the sponge: a quadratic profile of width nb whose
+// round-trip amplitude decay at normal incidence is 10^-3, exp(-2 int eta dx
+// / v) = 10^-3 with int_0^{nb dx} eta_max (x / (nb dx))^2 dx = eta_max nb dx / 3,
+// i.e. eta_max = 3 v_max ln(10^3) / (2 nb dx).
+double default_eta_max(double vmax, int nb, double dx)
+{
+    return nb > 0 ? 3.0 * vmax * std::log(1000.0) / (2.0 * nb * dx) : 0.0;
 }
 
 struct Policy {
@@ -356,6 +368,16 @@ void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *
     *nzc = (g.nz + z - 1) / z;
 }
 
+// z-chunk order and marching direction of 3-D step launches (kTile* flags).
+int tile_flags(const Geometry &g)
+{
+    if (g.ndim != 3) return 0;
+    int f = 0;
+    if (const char *e = getenv("FWI_ZFAST")) f |= atoi(e) ? kTileZFast : 0;
+    if (const char *e = getenv("FWI_ZALT")) f |= atoi(e) ? kTileZAlt : 0;
+    return f;
+}
+
 int gather_threads(const Geometry &g)
 {
     return g.ndim == 3 ? 64 * block_waves(shape_code(false, g.M)) : 64;
@@ -462,6 +484,9 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
     const double cfl = (double)vmax * p->dt / p->dx;
     const double lim = std::sqrt(4.0 / (p->ndim * max_symbol(p->order)));
     if (cfl > lim) return fail(FWI_ECFL, "v_max dt / dx = %.4f exceeds %.4f", cfl, lim);
+    // sponge strength: as given, or (eta_max < 0) the default for this model
+    const double eta_max = p->eta_max >= 0.f ? (double)p->eta_max
+                                             : default_eta_max(vmax, g.nb, p->dx);
 
     // receiver offsets and duplicate chains (receivers sharing a cell)
     auto offset = [&](const int32_t *q) -> int64_t {
@@ -491,6 +516,7 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
     for (int a = 0; a < 2; ++a) {
         tiles_for(g, S, a == 1, &til[a].ntx, &til[a].nty, &til[a].nzc, &til[a].zc);
         til[a].ntiles = til[a].ntx * til[a].nty * til[a].nzc;
+        til[a].flags = tile_flags(g);
     }
     c.gthreads = gather_threads(g);
     const int ng = (R + c.gthreads - 1) / c.gthreads;
@@ -547,7 +573,7 @@ int stage(Ctx &c, const float *v, const float *src, const int32_t *src_pos,
         J.nz = g.nz; J.ny = g.ny; J.nx = g.nx;
         J.pitch = g.pitch; J.nya = g.nya; J.nb = g.nb;
         J.plane = g.plane; J.fstride = g.fstride;
-        J.eta_dt = g.nb > 0 ? (float)((double)p->eta_max * p->dt / ((double)g.nb * g.nb)) : 0.f;
+        J.eta_dt = g.nb > 0 ? (float)(eta_max * p->dt / ((double)g.nb * g.nb)) : 0.f;
         J.src_scale = (float)((double)p->dt * p->dt / cell);
         J.tile[0] = til[0];
         J.tile[1] = til[1];
@@ -900,6 +926,41 @@ int backward_phase(Ctx &c)
     return FWI_OK;
 }
 
+// Wavefield watchdog: FWI_ENONFINITE if forward level L (in the ring) of any
+// shot holds a non-finite value.  Synchronises the stream.  An unstable or
+// NaN-fed propagation ends with a non-finite field, so one check of the last
+// level covers the whole run at the cost of one read of it.
+int check_level(Ctx &c, int L)
+{
+    float *d = c.f_at(c.L.vstats, true);
+    launch_nonfinite_level(c.d_jobs, c.p->nshots, L, d, c.st);
+    HIP_TRY(hipGetLastError());
+    std::vector<float> h((size_t)vstats_blocks());
+    HIP_TRY(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    float bad = 0.f;
+    for (float x : h) bad += x;
+    if (bad > 0.f) return fail(FWI_ENONFINITE, "the wavefield at step %d is not finite", L);
+    return FWI_OK;
+}
+
+// FWI_ENONFINITE if a model-grid output (dv) holds a non-finite value.
+// Synchronises the stream.
+int check_model(Ctx &c, const float *a)
+{
+    float *d = c.f_at(c.L.vstats, true);
+    launch_vstats(a, c.g.model_cells, d, c.st);
+    HIP_TRY(hipGetLastError());
+    const int B = vstats_blocks();
+    std::vector<float> h(3 * (size_t)B);
+    HIP_TRY(hipMemcpyAsync(h.data(), d, h.size() * 4, hipMemcpyDeviceToHost, c.st));
+    HIP_TRY(hipStreamSynchronize(c.st));
+    float bad = 0.f;
+    for (int i = 0; i < B; ++i) bad += h[2 * B + i];
+    if (bad > 0.f) return fail(FWI_ENONFINITE, "the gradient is not finite");
+    return FWI_OK;
+}
+
 int fold(Ctx &c, const float *v, float *dv)
 {
     const Geometry &g = c.g;
@@ -1078,7 +1139,9 @@ int fwi_forward(const fwi_problem *prob, const float *v, const float *src,
         if (!src || (prob->nrec > 0 && !traces)) return fail(FWI_EINVAL, "NULL input/output array");
         st = stage(c, v, src, src_pos, rec_pos, prob->nrec > 0 ? traces : nullptr, nullptr, 0);
         if (st) return st;
-        return forward_phase(c, prob->nrec > 0);
+        st = forward_phase(c, prob->nrec > 0);
+        if (st) return st;
+        return check_level(c, prob->nt);
     } catch (const std::bad_alloc &) {
         return fail(FWI_EINVAL, "host allocation failed");
     } catch (...) {
@@ -1099,7 +1162,9 @@ int fwi_forward_ckpt(const fwi_problem *prob, const float *v, const float *src,
         if (!src || (prob->nrec > 0 && !traces)) return fail(FWI_EINVAL, "NULL input/output array");
         st = stage(c, v, src, src_pos, rec_pos, prob->nrec > 0 ? traces : nullptr, nullptr, 1);
         if (st) return st;
-        return forward_phase(c, prob->nrec > 0);
+        st = forward_phase(c, prob->nrec > 0);
+        if (st) return st;
+        return check_level(c, prob->nt);
     } catch (const std::bad_alloc &) {
         return fail(FWI_EINVAL, "host allocation failed");
     } catch (...) {
@@ -1123,7 +1188,9 @@ int fwi_backward(const fwi_problem *prob, const float *v, const float *src,
         if (st) return st;
         st = backward_phase(c);
         if (st) return st;
-        return fold(c, v, dv);
+        st = fold(c, v, dv);
+        if (st) return st;
+        return check_model(c, dv);
     } catch (const std::bad_alloc &) {
         return fail(FWI_EINVAL, "host allocation failed");
     } catch (...) {
@@ -1164,7 +1231,7 @@ int fwi_gradient(const fwi_problem *prob, const float *v, const float *src,
         HIP_TRY(hipMemcpyAsync(h_misfit, d_mis, sizeof(double), hipMemcpyDeviceToHost, c.st));
         HIP_TRY(hipStreamSynchronize(c.st));
         if (!std::isfinite(*h_misfit)) return fail(FWI_ENONFINITE, "misfit is not finite");
-        return FWI_OK;
+        return check_model(c, dv);
     } catch (const std::bad_alloc &) {
         return fail(FWI_EINVAL, "host allocation failed");
     } catch (...) {
@@ -1195,6 +1262,20 @@ int fwi_velocity_range(const float *v, int64_t n, float *h_vmin, float *h_vmax, 
     if (bad > 0.f) return fail(FWI_EINVAL, "velocity has non-finite values");
     *h_vmin = lo;
     *h_vmax = hi;
+    return FWI_OK;
+}
+
+int fwi_stream_probe(const float *a, const float *b, const float *c, float *out, int64_t n,
+                     int32_t variant, void *stream)
+{
+    if (!a || !b || !c || !out) return fail(FWI_EINVAL, "NULL array");
+    if (n < 4 || n % 4 != 0) return fail(FWI_EINVAL, "n must be a positive multiple of 4");
+    if (variant < 0 || variant > 15 || (variant & 3) == 3) return fail(FWI_EINVAL, "bad variant");
+    const uintptr_t al = reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
+                         reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(out);
+    if (al & 15) return fail(FWI_EINVAL, "arrays must be 16-byte aligned");
+    launch_stream_probe(a, b, c, out, n, variant, static_cast<hipStream_t>(stream));
+    HIP_TRY(hipGetLastError());
     return FWI_OK;
 }
 

@@ -31,8 +31,9 @@ def misfit(v, obs, src, src_pos, rec_pos, cfg, workspace=None):
 
 
 def lbfgs(v0, obs, src, src_pos, rec_pos, cfg, iters=10, memory=5, vmin=None, vmax=None,
-          first_step=20.0, c1=1e-4, max_backtracks=8, log=None):
-    """Returns (v, history) with history[i] = misfit before iteration i (and the last)."""
+          first_step=20.0, c1=1e-4, max_backtracks=8, log=None, steps=None):
+    """Returns (v, history) with history[i] = misfit before iteration i (and the last).
+    If `steps` is a list, the accepted step length of each iteration is appended."""
     import torch
 
     from . import api
@@ -88,6 +89,8 @@ def lbfgs(v0, obs, src, src_pos, rec_pos, cfg, iters=10, memory=5, vmin=None, vm
                 Y.pop(0)
         v, g, phi = vt, gn, pn
         hist.append(phi)
+        if steps is not None:
+            steps.append(step)
         if log:
             log("iteration %d: misfit %.6e (step %.3g)" % (it, phi, step))
     return v, hist

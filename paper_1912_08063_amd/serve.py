@@ -52,6 +52,7 @@ class Result:
     misfit: Optional[float] = None
     seq: int = -1                  # completion index within the run
     work: int = 0                  # padded cells x program operations, at admission
+    error: Optional[str] = None    # set when the request was refused or failed
 
     @property
     def latency(self):
@@ -251,6 +252,7 @@ class Server:
             if a.dv is not None:
                 res.dv = a.dv.cpu().numpy()
         _lib.fwi_job_destroy(a.handle)
+        a.handle = None
         return res
 
     def _select(self, active):
@@ -272,16 +274,39 @@ class Server:
         return chosen
 
     # ------------------------------------------------------------------- loop
+    def _reject(self, req: Request, now, err):
+        """A request that is refused or fails: retired with its error."""
+        return Result(req.rid, req.kind, req.arrival, now, now, error=str(err))
+
     def run(self, requests: List[Request], realtime=True, log=None):
-        """Serves the stream; returns (results, report dict)."""
+        """Serves the stream; returns (results, report dict).  A request that
+        the library refuses (shapes, stability limit, positions, memory) or
+        whose work fails is retired with Result.error set; the others are
+        served as if it had not been there."""
+        active = []
+        try:
+            return self._run(requests, realtime, log, active)
+        finally:
+            # every job handle still held (an exception left the loop) is freed
+            from . import _lib
+            for a in active:
+                if getattr(a, "handle", None):
+                    _lib.fwi_job_destroy(a.handle)
+                    a.handle = None
+
+    def _run(self, requests, realtime, log, active):
         from . import _lib
         torch = self.torch
-        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
-        for r in pending:
-            if r.kind == "gradient" and r.obs is None:
-                raise ValueError("gradient request %d has no observed data" % r.rid)
-            self.check_request(r)
-        active, results = [], []
+        results = []
+        pending = []
+        for r in sorted(requests, key=lambda r: (r.arrival, r.rid)):
+            try:
+                if r.kind == "gradient" and r.obs is None:
+                    raise ValueError("gradient request %d has no observed data" % r.rid)
+                self.check_request(r)
+                pending.append(r)
+            except ValueError as e:
+                results.append(self._reject(r, r.arrival, e))
         used = 0
         cells = 0
         stream = torch.cuda.current_stream(self.device).cuda_stream
@@ -299,17 +324,27 @@ class Server:
                 r = pending[0]
                 if realtime and r.arrival > now:
                     break
-                need = self.footprint(r)
+                try:
+                    need = self.footprint(r)
+                except _lib.FwiError as e:
+                    pending.pop(0)
+                    results.append(self._reject(r, now, e))
+                    continue
                 if used + need > self.budget and active:
                     break
                 if (self.policy == "fifo" and self.fill_cells and active
                         and cells + r.problem.padded_cells > self.fill_cells):
                     break
-                if need > self.budget:
-                    raise MemoryError("request %d needs %d bytes > budget %d" %
-                                      (r.rid, need, self.budget))
                 pending.pop(0)
-                a = self._admit(r, now)
+                if need > self.budget:
+                    results.append(self._reject(r, now, "needs %d bytes, more than the budget %d"
+                                                % (need, self.budget)))
+                    continue
+                try:
+                    a = self._admit(r, now)
+                except _lib.FwiError as e:
+                    results.append(self._reject(r, now, e))
+                    continue
                 used += a.footprint
                 cells += r.problem.padded_cells
                 active.append(a)
@@ -319,13 +354,32 @@ class Server:
                 elif pending:
                     virtual = max(virtual, pending[0].arrival)
                 continue
-            _lib.fwi_jobs_advance([a.handle for a in self._select(active)], self.chunk,
-                                  self.ws.data_ptr(), ws_bytes, stream)
+            chosen = self._select(active)
+            failed = {}
+            try:
+                _lib.fwi_jobs_advance([a.handle for a in chosen], self.chunk,
+                                      self.ws.data_ptr(), ws_bytes, stream)
+            except _lib.FwiError:
+                # isolate the failing job(s): the others advance one by one
+                for a in chosen:
+                    try:
+                        _lib.fwi_jobs_advance([a.handle], self.chunk, self.ws.data_ptr(),
+                                              ws_bytes, stream)
+                    except _lib.FwiError as e:
+                        failed[id(a)] = e
             torch.cuda.synchronize(self.device)
             chunks += 1
             now = clock() if realtime else virtual
             still = []
             for a in active:
+                if id(a) in failed:
+                    results.append(self._reject(a.req, now, failed[id(a)]))
+                    results[-1].admitted = a.admitted
+                    _lib.fwi_job_destroy(a.handle)
+                    a.handle = None
+                    used -= a.footprint
+                    cells -= a.req.problem.padded_cells
+                    continue
                 done, _ = _lib.fwi_job_query(a.handle)
                 if done:
                     results.append(self._finish(a, now))
@@ -337,14 +391,16 @@ class Server:
                             len(results), a.req.rid, a.req.kind, results[-1].latency))
                 else:
                     still.append(a)
-            active = still
+            active[:] = still
         makespan = (clock() if realtime else virtual)
-        lat = np.array([r.latency for r in results])
+        ok = [r for r in results if r.error is None]
+        lat = np.array([r.latency for r in ok])
         report = {
-            "requests": len(results), "chunks": chunks, "chunk_steps": self.chunk,
+            "requests": len(ok), "failed": len(results) - len(ok),
+            "chunks": chunks, "chunk_steps": self.chunk,
             "max_active": self.max_active, "fill_cells": self.fill_cells, "policy": self.policy,
             "makespan_s": makespan,
-            "shots_per_s": len(results) / makespan if makespan > 0 else None,
+            "shots_per_s": len(ok) / makespan if makespan > 0 else None,
             "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
             "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
             "mean_latency_s": float(lat.mean()) if len(lat) else None,

@@ -59,7 +59,7 @@ def test_cfl_limit_matches_oracle(ndim, order):
 
 
 @pytest.mark.parametrize("bad", [dict(ndim=4), dict(order=6), dict(dx=0.0), dict(dt=-1.0),
-                                 dict(nt=0), dict(nsponge=-1), dict(eta_max=-1.0),
+                                 dict(nt=0), dict(nsponge=-1), dict(eta_max=float("nan")),
                                  dict(nshots=0), dict(nrec=-2), dict(shape=(0, 10))])
 def test_invalid_problems_rejected_before_any_device_call(bad):
     p = _prob(**bad)

@@ -17,23 +17,30 @@ def test_more_than_one_gpu_exits_with_a_message():
 def test_recorded_traffic_only_for_the_profiled_sources(tmp_path, monkeypatch):
     """roofline.traffic comes from rocprofv3 counter runs recorded with the
     SHA-1 of the kernel and runtime sources they measured: it is reported only
-    while both files are unchanged, and is null otherwise."""
+    while those files are unchanged, and is null otherwise."""
+    import hashlib
     import json
     import shutil
     sys.path.insert(0, ROOT)
     import bench
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_k_step3d_fwd_layered304.json")))
-    assert bench.recorded_traffic() == rec["traffic_bytes_per_launch"]
     assert rec["traffic_bytes_per_launch"] == (rec["fetch_bytes_per_launch"]
                                                + rec["write_bytes_per_launch"])
-    # a copy of the tree with one source byte changed
+    assert rec.get("measured_commit")
+    # the committed record names the sources it measured: it is reported
+    # exactly when the tree's sources still hash to those values
+    same = all(hashlib.sha1(open(os.path.join(ROOT, src), "rb").read()).hexdigest() == h
+               for src, h in rec["sources_sha1"].items())
+    assert bench.recorded_traffic() == (rec["traffic_bytes_per_launch"] if same else None)
+    # a tree whose sources match the record, then one byte changed
     fake = tmp_path / "repo"
     os.makedirs(fake / "profiles")
-    shutil.copy(os.path.join(ROOT, "profiles", "traffic_k_step3d_fwd_layered304.json"),
-                fake / "profiles")
+    fake_rec = dict(rec, sources_sha1={})
     for src in rec["sources_sha1"]:
         os.makedirs(fake / os.path.dirname(src), exist_ok=True)
         shutil.copy(os.path.join(ROOT, src), fake / src)
+        fake_rec["sources_sha1"][src] = hashlib.sha1(open(fake / src, "rb").read()).hexdigest()
+    json.dump(fake_rec, open(fake / "profiles" / "traffic_k_step3d_fwd_layered304.json", "w"))
     monkeypatch.setattr(bench, "ROOT", str(fake))
     assert bench.recorded_traffic() == rec["traffic_bytes_per_launch"]
     first = next(iter(rec["sources_sha1"]))

@@ -2,7 +2,9 @@
 
 * 2-D gradient workload (1024x320, 3000 steps): one shot's misfit and dv, a
   four-shot batched forward, and the whole 32-shot batched gradient that
-  bench.py times (marked slow), element by element against the FP64 oracle.
+  bench.py times (marked slow), element by element against the FP64 oracle;
+  the same 32 shots through torch.autograd (FWIForward) against the oracle,
+  and against central differences of the misfit along smooth directions.
 * 3-D forward workload (256^3 + sponge): the full grid and receiver plane
   against the oracle over the first 100 steps, and the whole 2000-step run
   that bench.py times (marked slow: about two minutes of the oracle).  The
@@ -37,18 +39,86 @@ def test_shots_2d_single_shot_gradient_full():
     assert rel_l2(dv_g, dv_o) <= 1e-3, rel_l2(dv_g, dv_o)
 
 
-@pytest.mark.slow
-def test_shots_2d_all_shots_batched_gradient_full():
-    """The benchmarked gradient call itself: 32 shots in shared launches, 3000
-    steps, every-50 checkpoints; misfit and dv summed over the shots against
-    the oracle's (about two minutes of the oracle)."""
+@pytest.fixture(scope="module")
+def shots_2d_oracle():
+    """The 2-D gradient workload (32 shots, 3000 steps) with the oracle's
+    observed data on the truth model and its misfit and dv on the start model
+    (about two minutes of the oracle), shared by the tests below."""
     P = f32(wl.shots_2d(nshots=32))
     obs = np.asarray(oracle_forward(P), np.float32).astype(np.float64)
     v0 = np.asarray(P.v_start, np.float32).astype(np.float64)
-    mis_g, dv_g, _ = gpu_gradient(P, v0, obs, "every:50")
     mis_o, dv_o = oracle_gradient(P, v0, obs)
+    return P, obs, v0, mis_o, dv_o
+
+
+@pytest.mark.slow
+def test_shots_2d_all_shots_batched_gradient_full(shots_2d_oracle):
+    """The benchmarked gradient call itself: 32 shots in shared launches, 3000
+    steps, every-50 checkpoints; misfit and dv summed over the shots against
+    the oracle's."""
+    P, obs, v0, mis_o, dv_o = shots_2d_oracle
+    mis_g, dv_g, _ = gpu_gradient(P, v0, obs, "every:50")
     assert abs(mis_g - mis_o) <= 1e-3 * mis_o
     assert rel_l2(dv_g, dv_o) <= 1e-3, rel_l2(dv_g, dv_o)
+
+
+def _autograd_c3(P, obs, v0):
+    """FWIForward on the whole 2-D gradient workload (every-50 checkpoints):
+    the loss ((traces - obs)^2).sum() in fp64 and v.grad."""
+    import torch
+    from paper_1912_08063_amd.autograd import FWIForward
+    vt, w, s, r = inputs(P, v0)
+    vt.requires_grad_(True)
+    tr = FWIForward.apply(vt, w, s, r, cfg(P, "every:50"))
+    loss = ((tr.double() - dev(obs, torch.float64)) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return float(loss), vt.grad.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.slow
+def test_shots_2d_autograd_full(shots_2d_oracle):
+    """The gradient workload at its own size through torch.autograd: all 32
+    shots, 3000 steps, every-50 checkpoints recomputed in the backward; v.grad
+    against the oracle's dv (1e-3) and the loss against its misfit."""
+    P, obs, v0, mis_o, dv_o = shots_2d_oracle
+    loss, g = _autograd_c3(P, obs, v0)
+    assert abs(loss - mis_o) <= 1e-3 * mis_o, (loss, mis_o)
+    assert rel_l2(g, dv_o) <= 1e-3, rel_l2(g, dv_o)
+
+
+def test_shots_2d_autograd_directional_differences():
+    """The same autograd gradient against central differences of the misfit
+    along three smooth directions (Gaussian bumps of 20 cells at three depths
+    and offsets, peak 1 m/s), the misfit of each perturbed model summed in
+    fp64 from the GPU forward's traces.  h = 10 m/s keeps the perturbation
+    within 0.7 % of the slowest velocity, where the misfit is close to
+    quadratic, and far above the fp32 noise of the traces (a few 1e-6
+    relative).  Bar: 1e-2 relative."""
+    import torch
+    from paper_1912_08063_amd import api
+    P = f32(wl.shots_2d(nshots=32))
+    vt, w, s, r = inputs(P)
+    obs_t = api.forward(vt, w, s, r, cfg(P))
+    obs = obs_t.cpu().numpy().astype(np.float64)
+    v0 = np.asarray(P.v_start, np.float32).astype(np.float64)
+    _, g = _autograd_c3(P, obs, v0)
+    nz, nx = v0.shape
+    zz, xx = np.meshgrid(np.arange(nz), np.arange(nx), indexing="ij")
+
+    def phi(v):
+        vv, _, _, _ = inputs(P, v)
+        d = api.forward(vv, w, s, r, cfg(P))
+        return float(((d.double() - obs_t.double()) ** 2).sum())
+
+    h = 10.0
+    for cz, cx in ((80, 300), (160, 512), (240, 760)):
+        direction = np.exp(-((zz - cz) ** 2 + (xx - cx) ** 2) / (2.0 * 20.0 ** 2))
+        direction /= direction.max()
+        an = float(np.sum(g * direction))
+        fd = (phi(v0 + h * direction) - phi(v0 - h * direction)) / (2 * h)
+        torch.cuda.synchronize()
+        assert abs(fd - an) <= 1e-2 * abs(an), (cz, cx, fd, an)
 
 
 def test_shots_2d_four_shot_batched_forward_full():

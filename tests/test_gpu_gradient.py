@@ -193,3 +193,34 @@ def test_lbfgs_reduces_the_misfit():
     assert all(b < a for a, b in zip(hist, hist[1:]))
     assert hist[-1] < 0.5 * hist[0]
     assert float((v - vt).norm()) < float((v0 - vt).norm())
+
+
+def test_lbfgs_matches_the_oracle_reference():
+    """Three iterations of the GPU inversion loop (misfit and gradient from the
+    HIP library, fp32 models) against the same iterations of the FP64
+    reference over the oracle (oracle/lbfgs.py, written separately from the
+    textbook algorithm): the misfit history to 1e-3 relative, the accepted
+    steps equal, and the model update to 1e-2 of its size."""
+    import torch
+    from oracle import lbfgs as ref
+    from paper_1912_08063_amd import api, inversion
+    P = f32(wl.small_2d(nz=40, nx=96, nt=260, nshots=4, nrec=48))
+    vt, w, s, r = inputs(P)
+    c = cfg(P, "every:20")
+    obs_t = api.forward(vt, w, s, r, c)
+    obs = obs_t.cpu().numpy().astype(np.float64)      # the same data on both sides
+    v0 = np.asarray(wl.smooth(P.v, 4.0), np.float32).astype(np.float64)
+    lo, hi = float(P.v.min()) - 100.0, float(P.v.max()) + 100.0
+    steps_g = []
+    v, hist = inversion.lbfgs(dev(v0, torch.float32), obs_t, w, s, r, c, iters=3, vmin=lo,
+                              vmax=hi, steps=steps_g)
+    torch.cuda.synchronize()
+    vr, hr, steps_r = ref.fwi(v0, P.wavelet, P.src_pos, P.rec_pos, obs, P.dx, P.dt, P.order,
+                              P.nb, P.eta_max, iters=3, vmin=lo, vmax=hi)
+    assert len(hist) == len(hr) == 4
+    for a, b in zip(hist, hr):
+        assert abs(a - b) <= 1e-3 * b, (hist, hr)
+    assert steps_g == steps_r
+    up_g = v.cpu().numpy().astype(np.float64) - v0
+    up_r = vr - v0
+    assert rel_l2(up_g, up_r) <= 1e-2, rel_l2(up_g, up_r)
