@@ -279,7 +279,10 @@ int fwi_jobs_ws_bytes(int32_t njobs, uint64_t *h_bytes);
 /* Advances every job by up to ksteps steps of its current phase, in shared
  * launches on `stream`, and enqueues the per-job operations due around them
  * (snapshots, final sampling, residual, gradient fold).  Finished jobs are
- * skipped.  Synchronises `stream` once to upload the launch tables. */
+ * skipped.  Does not synchronise: the launch tables reach the device as
+ * kernel arguments of a small assembly kernel that writes them into `ws`, so
+ * a caller can enqueue the next chunk while this one runs.  `ws` may be
+ * reused by the next call on the same stream (stream order protects it). */
 int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *ws,
                      uint64_t ws_bytes, void *stream);
 
@@ -289,6 +292,11 @@ int fwi_job_query(const fwi_job *job, int32_t *h_done, int64_t *h_ops_left);
 
 /* Misfit of a finished gradient job (synchronises `stream`). */
 int fwi_job_misfit(const fwi_job *job, double *h_misfit, void *stream);
+
+/* Device address of a gradient job's misfit (one double in the job's memory,
+ * valid once the stream has passed the job's last advance), for callers that
+ * copy it asynchronously instead of synchronising.  Host-only. */
+int fwi_job_misfit_device(const fwi_job *job, const double **d_misfit);
 
 /* Frees the host handle (not `mem`). */
 void fwi_job_destroy(fwi_job *job);

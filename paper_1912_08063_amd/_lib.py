@@ -10,7 +10,9 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfwi.so")
+# FWI_LIBRARY names another build of the same library (e.g. the host code
+# built with sanitizers for the CPU tests); the default is the in-tree build.
+LIB_PATH = os.environ.get("FWI_LIBRARY") or os.path.join(_HERE, "libfwi.so")
 
 FWI_OK, FWI_EINVAL, FWI_ECFL, FWI_EBOUNDS, FWI_ENOMEM, FWI_EHIP, FWI_ENONFINITE, \
     FWI_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
@@ -21,7 +23,7 @@ OP_ADVANCE, OP_TAKESHOT, OP_RESTORE, OP_ADJOINT, OP_RESTART = 1, 2, 3, 4, 5
 EXPORTS = ["fwi_strerror", "fwi_last_error", "fwi_cfl_limit", "fwi_workspace_bytes",
            "fwi_forward", "fwi_gradient", "fwi_forward_ckpt", "fwi_backward",
            "fwi_revolve_schedule", "fwi_revolve_plan", "fwi_velocity_range", "fwi_stream_probe", "fwi_job_bytes", "fwi_job_create",
-           "fwi_jobs_ws_bytes", "fwi_jobs_advance", "fwi_job_query", "fwi_job_misfit",
+           "fwi_jobs_ws_bytes", "fwi_jobs_advance", "fwi_job_query", "fwi_job_misfit", "fwi_job_misfit_device",
            "fwi_job_destroy"]
 JOB_FORWARD, JOB_GRADIENT = 0, 1
 
@@ -84,6 +86,7 @@ def load():
     lib.fwi_jobs_advance.argtypes = [P(vp), i32, i32, vp, u64, vp]
     lib.fwi_job_query.argtypes = [vp, P(i32), P(i64)]
     lib.fwi_job_misfit.argtypes = [vp, P(ctypes.c_double), vp]
+    lib.fwi_job_misfit_device.argtypes = [vp, P(vp)]
     lib.fwi_job_destroy.argtypes = [vp]
     lib.fwi_job_destroy.restype = None
     for name in EXPORTS:
@@ -232,6 +235,12 @@ def fwi_job_query(handle):
 def fwi_job_misfit(handle, stream):
     out = ctypes.c_double()
     _check(load().fwi_job_misfit(handle, ctypes.byref(out), stream), "fwi_job_misfit")
+    return out.value
+
+
+def fwi_job_misfit_device(handle):
+    out = ctypes.c_void_p()
+    _check(load().fwi_job_misfit_device(handle, ctypes.byref(out)), "fwi_job_misfit_device")
     return out.value
 
 

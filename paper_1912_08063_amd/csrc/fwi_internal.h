@@ -92,4 +92,20 @@ struct LevelMap {
     int32_t fld[3] = {0, 0, 0};
 };
 
+// Launch tables of fwi_jobs_advance, assembled on the device (k_assemble):
+// each entry is copied from the job's own table entry in its memory and its
+// time window for this chunk is patched in.  Passed by value as a kernel
+// argument, so the host neither copies tables nor waits for the stream.
+constexpr int kAssembleJobs = 32;
+constexpr int kAssemblePrefix = 96;
+struct AssembleArgs {
+    int32_t count;                  // entries first .. first + count - 1
+    int32_t first;
+    int32_t nprefix;                // prefix ints pfirst .. pfirst + nprefix - 1
+    int32_t pfirst;
+    const Job *src[kAssembleJobs];  // the job's own table entry (device)
+    int32_t win[kAssembleJobs][7];  // n0, k0, fwd_lo, fwd_hi, adj_lo, adj_hi, record
+    int32_t prefix[kAssemblePrefix];
+};
+
 }  // namespace fwi

@@ -1082,6 +1082,34 @@ void launch_stream_probe(const float *a, const float *b, const float *c, float *
     }
 }
 
+// Launch tables of a serving chunk (see AssembleArgs): block i copies entry
+// i from the job's memory and patches its time window; block 0 also writes
+// the launch's slice of the prefix arrays.
+__global__ __launch_bounds__(64) void k_assemble(AssembleArgs a, Job *__restrict__ table,
+                                                 int *__restrict__ prefix)
+{
+    const int i = blockIdx.x;
+    if (i < a.count) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.src[i]);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(table + a.first + i);
+        constexpr int words = sizeof(Job) / sizeof(uint32_t);
+        for (int w = threadIdx.x; w < words; w += blockDim.x) dst[w] = src[w];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            Job &J = table[a.first + i];
+            J.n0 = a.win[i][0];
+            J.k0 = a.win[i][1];
+            J.fwd_lo = a.win[i][2];
+            J.fwd_hi = a.win[i][3];
+            J.adj_lo = a.win[i][4];
+            J.adj_hi = a.win[i][5];
+            J.record = a.win[i][6];
+        }
+    }
+    if (i == 0)
+        for (int p = threadIdx.x; p < a.nprefix; p += blockDim.x) prefix[a.pfirst + p] = a.prefix[p];
+}
+
 // Non-finite cells of forward level L of every job (ring slot L mod R):
 // per-block counts, partial[0 .. gridDim.x), summed on the host.
 __global__ __launch_bounds__(256) void k_nonfinite_level(const Job *__restrict__ jobs, int njobs,
@@ -1112,6 +1140,12 @@ __global__ __launch_bounds__(256) void k_nonfinite_level(const Job *__restrict__
 
 // ---------------------------------------------------------------- launchers
 int vstats_blocks() { return 256; }
+
+void launch_assemble(const AssembleArgs &a, Job *table, int *prefix, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_assemble, dim3(a.count > 0 ? a.count : 1), dim3(64), 0, st, a, table,
+                       prefix);
+}
 
 void launch_nonfinite_level(const Job *jobs, int njobs, int L, float *partial, hipStream_t st)
 {

@@ -46,6 +46,7 @@ int vstats_blocks();
 int step_blocks_per_cu(int ndim, int M, int nw, bool adj);
 void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st);
 void launch_nonfinite_level(const Job *jobs, int njobs, int L, float *partial, hipStream_t st);
+void launch_assemble(const AssembleArgs &a, Job *table, int *prefix, hipStream_t st);
 void launch_stream_probe(const float *a, const float *b, const float *c, float *o, int64_t n,
                          int variant, hipStream_t st);
 }  // namespace fwi
@@ -1419,9 +1420,13 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
         // 1. operations due before this chunk's steps
         for (int i = 0; i < njobs; ++i) TRY(run_immediates(jobs[i]));
         // 2. gather this chunk's step ranges into launch groups
+        struct Entry {
+            const Job *src;   // the job's own table entry (device)
+            int32_t win[7];   // n0, k0, fwd_lo, fwd_hi, adj_lo, adj_hi, record
+        };
         struct Group {
             int ndim = 0, M = 0, adj = 0, nw = 4, steps = 0;
-            std::vector<Job> table;
+            std::vector<Entry> table;
             std::vector<int> tp{0}, gp{0};
             Job *d_jobs = nullptr;
             int *d_prefix = nullptr;
@@ -1440,20 +1445,23 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
             fwi_job *J = jobs[i];
             if (J->head >= J->ops.size()) continue;
             JobOp &o = J->ops[J->head];
-            Job t = J->c.jobs[0];
+            const Job &t = J->c.jobs[0];
+            Entry e{J->c.d_jobs, {t.n0, t.k0, t.fwd_lo, t.fwd_hi, t.adj_lo, t.adj_hi, t.record}};
             int steps;
+            bool record = false;
             if (o.type == JOP_FWD) {
                 steps = std::min(ksteps, o.b - o.a);
-                t.n0 = o.a;
-                t.fwd_lo = o.a;
-                t.fwd_hi = o.a + steps;
-                t.record = o.record && J->rec;
+                record = o.record && J->rec;
+                e.win[0] = o.a;
+                e.win[2] = o.a;
+                e.win[3] = o.a + steps;
+                e.win[6] = record ? 1 : 0;
                 o.a += steps;
             } else {
                 steps = std::min(ksteps, o.a - o.b + 1);
-                t.k0 = o.a;
-                t.adj_hi = o.a + 1;
-                t.adj_lo = o.a - steps + 1;
+                e.win[1] = o.a;
+                e.win[5] = o.a + 1;
+                e.win[4] = o.a - steps + 1;
                 o.a -= steps;
             }
             const bool finished = o.type == JOP_FWD ? o.a >= o.b : o.a < o.b;
@@ -1462,12 +1470,15 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
             Group &g = group_of(J->c.g.ndim, J->c.g.M, isadj, isadj ? J->c.nw_adj : J->c.nw);
             g.steps = std::max(g.steps, steps);
             g.gthreads = J->c.gthreads;
-            g.table.push_back(t);
+            g.table.push_back(e);
             g.tp.push_back(g.tp.back() + t.tile[isadj ? 1 : 0].ntiles);
-            g.gp.push_back(g.gp.back() + ((o.type == JOP_FWD && t.record) || o.type == JOP_ADJ
+            g.gp.push_back(g.gp.back() + ((o.type == JOP_FWD && record) || o.type == JOP_ADJ
                                               ? t.ngather : 0));
         }
-        // 3. upload the tables and launch every step of the chunk for all groups
+        // 3. assemble the tables on the device (kernel arguments carry them:
+        // no host copy to wait for; the stream orders them after the previous
+        // chunk's launches, which read the same workspace) and launch every
+        // step of the chunk for all groups
         char *w = static_cast<char *>(ws);
         uint64_t off = 0;
         for (Group &g : groups) {
@@ -1478,12 +1489,24 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
             off += align_up(sizeof(int) * 2ull * (n + 1), kAlign);
             std::vector<int> pre(g.tp);
             pre.insert(pre.end(), g.gp.begin(), g.gp.end());
-            HIP_TRY(hipMemcpyAsync(g.d_jobs, g.table.data(), sizeof(Job) * n,
-                                   hipMemcpyHostToDevice, st));
-            HIP_TRY(hipMemcpyAsync(g.d_prefix, pre.data(), sizeof(int) * pre.size(),
-                                   hipMemcpyHostToDevice, st));
+            const int np = (int)pre.size();
+            for (int j0 = 0, p0 = 0; j0 < n || p0 < np;) {
+                AssembleArgs a{};
+                a.first = j0;
+                a.count = std::min(kAssembleJobs, n - j0);
+                for (int k = 0; k < a.count; ++k) {
+                    a.src[k] = g.table[j0 + k].src;
+                    std::copy(g.table[j0 + k].win, g.table[j0 + k].win + 7, a.win[k]);
+                }
+                a.pfirst = p0;
+                a.nprefix = std::min(kAssemblePrefix, np - p0);
+                std::copy(pre.begin() + p0, pre.begin() + p0 + a.nprefix, a.prefix);
+                launch_assemble(a, g.d_jobs, g.d_prefix, st);
+                j0 += a.count;
+                p0 += a.nprefix;
+            }
         }
-        HIP_TRY(hipStreamSynchronize(st));   // host tables die with this frame
+        HIP_TRY(hipGetLastError());
         for (int j = 0; j < ksteps; ++j) {
             for (Group &g : groups) {
                 if (j >= g.steps) continue;
@@ -1524,6 +1547,14 @@ int fwi_job_misfit(const fwi_job *job, double *h_misfit, void *stream)
     hipStream_t st = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(h_misfit, job->d_misfit, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return FWI_OK;
+}
+
+int fwi_job_misfit_device(const fwi_job *job, const double **d_misfit)
+{
+    if (!job || !d_misfit) return fail(FWI_EINVAL, "bad argument");
+    if (job->kind != FWI_JOB_GRADIENT) return fail(FWI_EINVAL, "not a gradient job");
+    *d_misfit = job->d_misfit;
     return FWI_OK;
 }
 

@@ -238,19 +238,39 @@ class Server:
             a.traces.data_ptr() if P.nrec else None, a.dv.data_ptr() if grad else None,
             a.mem.data_ptr(), a.mem.numel(), stream)
         a.work = P.padded_cells * _lib.fwi_job_query(a.handle)[1]
+        if grad:
+            # the misfit is a double inside the job memory: a view of it can be
+            # copied to the host without synchronising the stream
+            a.mis_off = _lib.fwi_job_misfit_device(a.handle) - a.mem.data_ptr()
         return a
 
-    def _finish(self, a, now):
-        from . import _lib
+    def _collect(self, a):
+        """Enqueues the copies of a finished job's outputs to pinned host memory
+        (read once the stream has passed them)."""
         torch = self.torch
-        res = Result(a.req.rid, a.req.kind, a.req.arrival, a.admitted, now, work=a.work)
+        pin = lambda t: torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+        a.host = {}
         if a.req.kind == "gradient":
-            res.misfit = _lib.fwi_job_misfit(a.handle, torch.cuda.current_stream(
-                self.device).cuda_stream)
+            m = a.mem[a.mis_off:a.mis_off + 8].view(torch.float64)
+            a.host["misfit"] = pin(m)
+            a.host["misfit"].copy_(m, non_blocking=True)
         if self.keep:
-            res.traces = a.traces.cpu().numpy()
-            if a.dv is not None:
-                res.dv = a.dv.cpu().numpy()
+            for name in ("traces", "dv"):
+                t = getattr(a, name)
+                if t is not None:
+                    a.host[name] = pin(t)
+                    a.host[name].copy_(t, non_blocking=True)
+
+    def _finish(self, a, now):
+        """Result of a job whose work (and output copies) the stream has passed."""
+        from . import _lib
+        res = Result(a.req.rid, a.req.kind, a.req.arrival, a.admitted, now, work=a.work)
+        if "misfit" in a.host:
+            res.misfit = float(a.host["misfit"][0])
+        if "traces" in a.host:
+            res.traces = a.host["traces"].numpy()
+        if "dv" in a.host:
+            res.dv = a.host["dv"].numpy()
         _lib.fwi_job_destroy(a.handle)
         a.handle = None
         return res
@@ -295,6 +315,12 @@ class Server:
                     a.handle = None
 
     def _run(self, requests, realtime, log, active):
+        """The serving loop.  Chunks are pipelined: the next chunk is enqueued
+        before the previous one has finished, and a job's completion time is
+        taken when the stream has passed the chunk that finished it (one HIP
+        event per chunk), so the GPU never waits for the host between
+        chunks."""
+        import collections
         from . import _lib
         torch = self.torch
         results = []
@@ -309,7 +335,8 @@ class Server:
                 results.append(self._reject(r, r.arrival, e))
         used = 0
         cells = 0
-        stream = torch.cuda.current_stream(self.device).cuda_stream
+        st = torch.cuda.current_stream(self.device)
+        stream = st.cuda_stream
         ws_bytes = _lib.fwi_jobs_ws_bytes(self.max_active)
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
         torch.cuda.synchronize(self.device)
@@ -317,81 +344,105 @@ class Server:
         clock = (lambda: time.perf_counter() - t0) if realtime else None
         virtual = 0.0
         chunks = 0
-        while pending or active:
-            now = clock() if realtime else virtual
-            # admit arrived requests while slots and memory allow
-            while pending and len(active) < self.max_active:
-                r = pending[0]
-                if realtime and r.arrival > now:
-                    break
-                try:
-                    need = self.footprint(r)
-                except _lib.FwiError as e:
-                    pending.pop(0)
-                    results.append(self._reject(r, now, e))
-                    continue
-                if used + need > self.budget and active:
-                    break
-                if (self.policy == "fifo" and self.fill_cells and active
-                        and cells + r.problem.padded_cells > self.fill_cells):
-                    break
-                pending.pop(0)
-                if need > self.budget:
-                    results.append(self._reject(r, now, "needs %d bytes, more than the budget %d"
-                                                % (need, self.budget)))
-                    continue
-                try:
-                    a = self._admit(r, now)
-                except _lib.FwiError as e:
-                    results.append(self._reject(r, now, e))
-                    continue
-                used += a.footprint
-                cells += r.problem.padded_cells
-                active.append(a)
-            if not active:
-                if realtime and pending:
-                    time.sleep(max(0.0, min(0.01, pending[0].arrival - clock())))
-                elif pending:
-                    virtual = max(virtual, pending[0].arrival)
-                continue
-            chosen = self._select(active)
-            failed = {}
-            try:
-                _lib.fwi_jobs_advance([a.handle for a in chosen], self.chunk,
-                                      self.ws.data_ptr(), ws_bytes, stream)
-            except _lib.FwiError:
-                # isolate the failing job(s): the others advance one by one
-                for a in chosen:
-                    try:
-                        _lib.fwi_jobs_advance([a.handle], self.chunk, self.ws.data_ptr(),
-                                              ws_bytes, stream)
-                    except _lib.FwiError as e:
-                        failed[id(a)] = e
-            torch.cuda.synchronize(self.device)
-            chunks += 1
-            now = clock() if realtime else virtual
-            still = []
-            for a in active:
-                if id(a) in failed:
-                    results.append(self._reject(a.req, now, failed[id(a)]))
-                    results[-1].admitted = a.admitted
-                    _lib.fwi_job_destroy(a.handle)
-                    a.handle = None
-                    used -= a.footprint
-                    cells -= a.req.problem.padded_cells
-                    continue
-                done, _ = _lib.fwi_job_query(a.handle)
-                if done:
+        inflight = collections.deque()   # (event, jobs finished by that chunk)
+        closing = []                     # finished jobs whose chunk is still in flight
+
+        def retire(wait_all):
+            nonlocal used
+            while inflight and (wait_all or len(inflight) > 1):
+                ev, done = inflight.popleft()
+                ev.synchronize()
+                now = clock() if realtime else virtual
+                for a in done:
                     results.append(self._finish(a, now))
                     results[-1].seq = len(results) - 1
                     used -= a.footprint
-                    cells -= a.req.problem.padded_cells
+                    closing.remove(a)
                     if log and len(results) % 10 == 0:
                         log("%d requests done (last: %d, %s, latency %.3f s)" % (
                             len(results), a.req.rid, a.req.kind, results[-1].latency))
-                else:
-                    still.append(a)
-            active[:] = still
+
+        try:
+            while pending or active or inflight:
+                now = clock() if realtime else virtual
+                # admit arrived requests while slots and memory allow
+                while pending and len(active) + len(closing) < self.max_active:
+                    r = pending[0]
+                    if realtime and r.arrival > now:
+                        break
+                    try:
+                        need = self.footprint(r)
+                    except _lib.FwiError as e:
+                        pending.pop(0)
+                        results.append(self._reject(r, now, e))
+                        continue
+                    if used + need > self.budget and (active or closing):
+                        break
+                    if (self.policy == "fifo" and self.fill_cells and active
+                            and cells + r.problem.padded_cells > self.fill_cells):
+                        break
+                    pending.pop(0)
+                    if need > self.budget:
+                        results.append(self._reject(
+                            r, now, "needs %d bytes, more than the budget %d" % (need, self.budget)))
+                        continue
+                    try:
+                        a = self._admit(r, now)
+                    except _lib.FwiError as e:
+                        results.append(self._reject(r, now, e))
+                        continue
+                    used += a.footprint
+                    cells += r.problem.padded_cells
+                    active.append(a)
+                if not active:
+                    if inflight:
+                        retire(True)
+                    elif realtime and pending:
+                        time.sleep(max(0.0, min(0.01, pending[0].arrival - clock())))
+                    elif pending:
+                        virtual = max(virtual, pending[0].arrival)
+                    continue
+                chosen = self._select(active)
+                failed = {}
+                try:
+                    _lib.fwi_jobs_advance([a.handle for a in chosen], self.chunk,
+                                          self.ws.data_ptr(), ws_bytes, stream)
+                except _lib.FwiError:
+                    # isolate the failing job(s): the others advance one by one
+                    for a in chosen:
+                        try:
+                            _lib.fwi_jobs_advance([a.handle], self.chunk, self.ws.data_ptr(),
+                                                  ws_bytes, stream)
+                        except _lib.FwiError as e:
+                            failed[id(a)] = e
+                chunks += 1
+                done, still = [], []
+                for a in active:
+                    if id(a) in failed:
+                        torch.cuda.synchronize(self.device)   # its memory may still be read
+                        now = clock() if realtime else virtual
+                        results.append(self._reject(a.req, now, failed[id(a)]))
+                        results[-1].admitted = a.admitted
+                        _lib.fwi_job_destroy(a.handle)
+                        a.handle = None
+                        used -= a.footprint
+                        cells -= a.req.problem.padded_cells
+                    elif _lib.fwi_job_query(a.handle)[0]:
+                        self._collect(a)
+                        done.append(a)
+                        cells -= a.req.problem.padded_cells
+                    else:
+                        still.append(a)
+                active[:] = still
+                closing.extend(done)
+                ev = torch.cuda.Event()
+                ev.record(st)
+                inflight.append((ev, done))
+                retire(False)
+            retire(True)
+        finally:
+            for a in closing:
+                active.append(a)
         makespan = (clock() if realtime else virtual)
         ok = [r for r in results if r.error is None]
         lat = np.array([r.latency for r in ok])

@@ -200,7 +200,7 @@ def test_lbfgs_matches_the_oracle_reference():
     HIP library, fp32 models) against the same iterations of the FP64
     reference over the oracle (oracle/lbfgs.py, written separately from the
     textbook algorithm): the misfit history to 1e-3 relative, the accepted
-    steps equal, and the model update to 1e-2 of its size."""
+    steps to 1e-3, and the model update to 1e-2 of its size."""
     import torch
     from oracle import lbfgs as ref
     from paper_1912_08063_amd import api, inversion
@@ -220,7 +220,9 @@ def test_lbfgs_matches_the_oracle_reference():
     assert len(hist) == len(hr) == 4
     for a, b in zip(hist, hr):
         assert abs(a - b) <= 1e-3 * b, (hist, hr)
-    assert steps_g == steps_r
+    # the same backtracking decisions: accepted steps agree to rounding (the
+    # first is first_step / max|g|, the others 1 / 2^k)
+    np.testing.assert_allclose(steps_g, steps_r, rtol=1e-3)
     up_g = v.cpu().numpy().astype(np.float64) - v0
     up_r = vr - v0
     assert rel_l2(up_g, up_r) <= 1e-2, rel_l2(up_g, up_r)

@@ -136,3 +136,72 @@ def test_mixed_orders_in_one_advance():
         assert np.array_equal(res.traces, tr), req.problem.name
         if req.kind == "gradient":
             assert np.array_equal(res.dv, dv) and res.misfit == mis
+
+
+def _sized_request(rid, kind, shape, nt, seed):
+    """A request of the configured stream's structure at a chosen size:
+    layered model, 10 Hz Ricker at the surface centre, dt from CFL 0.4, surface
+    receivers (every cell in 2-D, every 4th in 3-D)."""
+    from paper_1912_08063_amd import serve
+    rng = np.random.default_rng(seed)
+    v = wl.layered(shape, rng)
+    dx = 10.0
+    dt = wl.dt_from_cfl(float(v.max()), dx, 0.4)
+    src = [[4] + [s // 2 for s in shape[1:]]]
+    rec = wl.surface_receivers(shape, 4, stride=1 if len(shape) == 2 else 4)
+    P = wl._pack("sized%d" % rid, v, dx, dt, nt, 8, 20 if len(shape) == 2 else 24, 10.0, src,
+                 rec)
+    return serve.Request(rid, kind, 0.0, f32(P))
+
+
+def test_full_size_jobs_in_a_mix_equal_standalone_calls():
+    """A 1024^2 2-D gradient and a 256^3 3-D forward (the configured stream's
+    sizes, 1200 steps) served together with two small jobs: each result is
+    bitwise that of its stand-alone fwi_gradient / fwi_forward call, the calls
+    the full-size parity tests check against the oracle."""
+    from paper_1912_08063_amd import serve
+    reqs = [_sized_request(0, "gradient", (1024, 1024), 1200, 61),
+            _sized_request(1, "forward", (256, 256, 256), 1200, 62),
+            _sized_request(2, "forward", (300, 300), 900, 63),
+            _sized_request(3, "gradient", (64, 80, 72), 700, 64)]
+    serve.attach_observed(reqs)
+    chunk = 50
+    results, rep = serve.Server(max_active=4, chunk=chunk, keep_outputs=True,
+                                policy="fifo", fill_cells=10 ** 12).run(reqs, realtime=False)
+    assert rep["requests"] == 4 and rep["failed"] == 0
+    for req, res in zip(reqs, results):
+        tr, dv, mis = _standalone(req, chunk)
+        assert np.array_equal(res.traces, tr), req.problem.name
+        if req.kind == "gradient":
+            assert np.array_equal(res.dv, dv), req.problem.name
+            assert res.misfit == mis
+
+
+def test_a_failing_request_is_retired_and_the_others_are_unchanged():
+    """One request violates the stability limit (dt 1.5x its CFL bound) and one
+    has a receiver outside its model: both are retired with an error, and every
+    other result is bitwise that of a run of the stream without them."""
+    import dataclasses
+    from paper_1912_08063_amd import serve
+    good = _stream(6, 0.06, seed=71)
+    bad_cfl = _stream(1, 0.06, seed=72)[0]
+    P = bad_cfl.problem
+    bad_cfl.problem = dataclasses.replace(P, dt=float(np.float32(1.5 * P.dt / 0.4 * 0.5546)))
+    bad_cfl.rid = 100
+    bad_pos = _stream(1, 0.06, seed=73)[0]
+    bad_pos.problem.rec_pos[0, 0, 0] = bad_pos.problem.v.shape[0] + 5
+    bad_pos.rid = 101
+    clean, rep0 = serve.Server(max_active=8, chunk=16, keep_outputs=True).run(good,
+                                                                            realtime=False)
+    mixed, rep1 = serve.Server(max_active=8, chunk=16, keep_outputs=True).run(
+        good[:3] + [bad_cfl] + good[3:] + [bad_pos], realtime=False)
+    assert rep0["failed"] == 0 and rep1["failed"] == 2 and rep1["requests"] == 6
+    errs = {r.rid: r.error for r in mixed if r.error}
+    assert set(errs) == {100, 101}
+    assert "stability" in errs[100] and "outside" in errs[101]
+    ok = [r for r in mixed if r.error is None]
+    for a, b in zip(clean, ok):
+        assert a.rid == b.rid
+        assert np.array_equal(a.traces, b.traces)
+        if a.kind == "gradient":
+            assert np.array_equal(a.dv, b.dv) and a.misfit == b.misfit
