@@ -148,6 +148,23 @@ int fwi_forward(const fwi_problem *prob, const float *v, const float *src,
                 void *ws, uint64_t ws_bytes, void *stream);
 
 /*
+ * fwi_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, bitwise the same traces, with the workspace taken
+ * from a fixed array the library holds on each GPU it runs on (128 MiB,
+ * kept until the process ends) instead of a caller's `ws`.  The caller
+ * passes only inputs and outputs.  Calls no hipMalloc or hipFree.  The
+ * array is shared by every call on the same GPU: calls that overlap on one
+ * GPU (other streams, other host threads) race; serialise them.  Each call
+ * initialises every part of the array it reads.  FWI_ENOMEM if the problem
+ * needs more workspace than the array holds (fwi_workspace_bytes, mode
+ * FWI_MODE_FORWARD); otherwise the errors of fwi_forward.
+ */
+int fwi_forward_noalloc(const fwi_problem *prob, const float *v, const float *src,
+                        const int32_t *src_pos, const int32_t *rec_pos, float *traces,
+                        void *stream);
+
+/*
  * Misfit (Eq. 1) and its gradient with respect to v: forward with
  * checkpoints, residual 2 (d - d_obs), adjoint propagation and the
  * imaging-condition gradient, recomputing the forward field as `ckpt` says.

@@ -21,7 +21,7 @@ CKPT_ALL, CKPT_EVERY, CKPT_REVOLVE = 0, 1, 2
 OP_ADVANCE, OP_TAKESHOT, OP_RESTORE, OP_ADJOINT, OP_RESTART = 1, 2, 3, 4, 5
 
 EXPORTS = ["fwi_strerror", "fwi_last_error", "fwi_cfl_limit", "fwi_workspace_bytes",
-           "fwi_forward", "fwi_gradient", "fwi_forward_ckpt", "fwi_backward",
+           "fwi_forward", "fwi_forward_noalloc", "fwi_gradient", "fwi_forward_ckpt", "fwi_backward",
            "fwi_revolve_schedule", "fwi_revolve_plan", "fwi_velocity_range", "fwi_stream_probe", "fwi_job_bytes", "fwi_job_create",
            "fwi_jobs_ws_bytes", "fwi_jobs_advance", "fwi_job_query", "fwi_job_misfit", "fwi_job_misfit_device",
            "fwi_job_destroy"]
@@ -70,6 +70,7 @@ def load():
     lib.fwi_cfl_limit.argtypes = [i32, i32, P(ctypes.c_double)]
     lib.fwi_workspace_bytes.argtypes = [prob, i32, ck, P(u64)]
     lib.fwi_forward.argtypes = [prob, vp, vp, vp, vp, vp, vp, u64, vp]
+    lib.fwi_forward_noalloc.argtypes = [prob, vp, vp, vp, vp, vp, vp]
     lib.fwi_gradient.argtypes = [prob, vp, vp, vp, vp, vp, ck, P(ctypes.c_double), vp, vp, vp,
                                  u64, vp]
     lib.fwi_forward_ckpt.argtypes = [prob, vp, vp, vp, vp, ck, vp, vp, u64, vp, u64, vp]
@@ -127,6 +128,11 @@ def fwi_workspace_bytes(prob, mode, ckpt=None):
 def fwi_forward(prob, v, src, src_pos, rec_pos, traces, ws, ws_bytes, stream):
     _check(load().fwi_forward(ctypes.byref(prob), v, src, src_pos, rec_pos, traces, ws,
                               ws_bytes, stream), "fwi_forward")
+
+
+def fwi_forward_noalloc(prob, v, src, src_pos, rec_pos, traces, stream):
+    _check(load().fwi_forward_noalloc(ctypes.byref(prob), v, src, src_pos, rec_pos, traces,
+                                      stream), "fwi_forward_noalloc")
 
 
 def fwi_gradient(prob, v, src, src_pos, rec_pos, obs, ckpt, dv, traces_or_null, ws, ws_bytes,

@@ -29,6 +29,9 @@ constexpr int kGatherThreads = 256;
 constexpr int32_t kTileZFast = 1;
 constexpr int32_t kTileZAlt = 2;
 
+// Size of the fixed per-GPU workspace of fwi_forward_noalloc.
+constexpr uint64_t kScratchBytes = 128ull << 20;
+
 struct Job {
     // geometry of the padded grid and its field layout
     int32_t nz, ny, nx;    // padded grid (ny == 1 in 2-D)

@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "fwi_internal.h"
 
 namespace fwi {
@@ -1136,6 +1138,31 @@ __global__ __launch_bounds__(256) void k_nonfinite_level(const Job *__restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// ------------------------------------------------- fixed per-GPU workspace
+// The workspace of fwi_forward_noalloc, for callers that cannot allocate
+// device memory: one array per GPU the library runs on, held until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol): it looks up each device's own
+// address once, with that device current, and passes that address.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+int scratch_address(void **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return -1;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return -1;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return 0;
 }
 
 // ---------------------------------------------------------------- launchers

@@ -47,6 +47,7 @@ int step_blocks_per_cu(int ndim, int M, int nw, bool adj);
 void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st);
 void launch_nonfinite_level(const Job *jobs, int njobs, int L, float *partial, hipStream_t st);
 void launch_assemble(const AssembleArgs &a, Job *table, int *prefix, hipStream_t st);
+int scratch_address(void **ptr);
 void launch_stream_probe(const float *a, const float *b, const float *c, float *o, int64_t n,
                          int variant, hipStream_t st);
 }  // namespace fwi
@@ -1148,6 +1149,24 @@ int fwi_forward(const fwi_problem *prob, const float *v, const float *src,
     } catch (...) {
         return fail(FWI_EINVAL, "internal error");
     }
+}
+
+int fwi_forward_noalloc(const fwi_problem *prob, const float *v, const float *src,
+                        const int32_t *src_pos, const int32_t *rec_pos, float *traces,
+                        void *stream)
+{
+    uint64_t need = 0;
+    int st = fwi_workspace_bytes(prob, FWI_MODE_FORWARD, nullptr, &need);
+    if (st) return st;
+    if (need > kScratchBytes)
+        return fail(FWI_ENOMEM,
+                    "fwi_forward_noalloc: the problem needs %llu workspace bytes, more than the "
+                    "fixed %llu-byte workspace (use fwi_forward)",
+                    (unsigned long long)need, (unsigned long long)kScratchBytes);
+    void *ws = nullptr;
+    if (scratch_address(&ws) != 0)
+        return fail(FWI_EHIP, "fwi_forward_noalloc: no address for the fixed workspace");
+    return fwi_forward(prob, v, src, src_pos, rec_pos, traces, ws, kScratchBytes, stream);
 }
 
 int fwi_forward_ckpt(const fwi_problem *prob, const float *v, const float *src,
