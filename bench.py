@@ -453,6 +453,9 @@ def serve_section(nreq, scale, chunk):
     _, b = serve.Server(max_active=64, chunk=chunk).run(reqs, realtime=True)
     log("serving x%.2f batched: p50 %.3f p99 %.3f s" % (scale, b["p50_latency_s"],
                                                        b["p99_latency_s"]))
+    _, bf = serve.Server(max_active=64, chunk=chunk, policy="fifo").run(reqs, realtime=True)
+    log("serving x%.2f batched fifo: p50 %.3f p99 %.3f s" % (scale, bf["p50_latency_s"],
+                                                            bf["p99_latency_s"]))
     _, p = serve.Server(max_active=1, chunk=chunk).run(reqs, realtime=True)
     log("serving x%.2f plain: p50 %.3f p99 %.3f s" % (scale, p["p50_latency_s"],
                                                      p["p99_latency_s"]))
@@ -468,7 +471,8 @@ def serve_section(nreq, scale, chunk):
             "p99_tail_samples": max(1, int(round(0.01 * nreq))),
             "rate_per_s": round(rate, 3),
             "saturated_shots_per_s": round(sat["shots_per_s"], 3),
-            "batched": {k: round(b[k], 4) for k in keep},
+            "batched": dict({k: round(b[k], 4) for k in keep}, policy=b["policy"]),
+            "batched_fifo": dict({k: round(bf[k], 4) for k in keep}, policy=bf["policy"]),
             "plain": {k: round(p[k], 4) for k in keep}}
 
 

@@ -791,6 +791,145 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
     }
 }
 
+// 2-D step for grids too small to fill the GPU: one block per tile row of 64
+// columns and one cell per lane, every neighbour loaded straight from memory
+// (the fields are cache-resident at these sizes).  Nothing is marched, so a
+// launch costs one round of load latency instead of the 2M + 1 row warm-up
+// and serial row loop of k_step2d.  The arithmetic is k_step2d's, term by term
+// in the same order, so both kernels give bitwise the same fields.  Tiles are
+// one row tall (Tiling.zc == 1); the adjoint takes this row's receiver cells
+// from the tile's list, as k_step2d does row by row.
+template <int M, bool ADJ>
+__global__ __launch_bounds__(64) void k_step2d_direct(const Job *__restrict__ jobs,
+                                                      const int *__restrict__ prefix, int njobs,
+                                                      int step, int ttiles, int remap,
+                                                      LevelMap lm)
+{
+    constexpr int TX = kTileX;
+    constexpr Weights<M> W{};
+    constexpr int KD = kDiffRadii < M ? kDiffRadii : M;   // radii in difference form
+    __shared__ float sinj[ADJ ? TX : 1];   // adjoint source of this row
+
+    const int lane = threadIdx.x;
+    int b = blockIdx.x;
+    if (b >= ttiles) {
+        if constexpr (ADJ) return;
+        const int gb = b - ttiles;
+        const int j = find_job(prefix + njobs + 1, njobs, gb);
+        const Job *J = jobs + j;
+        gather_block(J, lm, (gb - prefix[njobs + 1 + j]) * blockDim.x + lane, J->n0 + step);
+        return;
+    }
+    if (remap) b = xcd_remap(b, ttiles);
+    const int j = find_job(prefix, njobs, b);
+    const Job *__restrict__ J = jobs + j;
+    const int n = ADJ ? J->k0 - step : J->n0 + step;
+    if (ADJ ? (n < J->adj_lo || n >= J->adj_hi) : (n < J->fwd_lo || n >= J->fwd_hi)) return;
+
+    const int nz = J->nz, nx = J->nx, pitch = J->pitch, nb = J->nb;
+    const int64_t fstride = J->fstride;
+    const Job::Tiling &T = J->tile[ADJ ? 1 : 0];
+    const int local = b - prefix[j];
+    const int tx = local % T.ntx;
+    const int z = local / T.ntx;   // one row per tile
+    if (z >= nz) return;
+
+    const gfloat *cur, *prv;
+    gfloat *out;
+    const gfloat *fwd = nullptr;
+    gfloat *grad = nullptr;
+    bool accum = false;
+    if constexpr (ADJ) {
+        cur = gptr(J->adj) + (int64_t)((n + 1) & 1) * fstride;
+        prv = gptr(J->adj) + (int64_t)(n & 1) * fstride;
+        out = gptr(J->adj) + (int64_t)(n & 1) * fstride;
+        accum = J->accumulate && n <= J->nt - 1;
+        fwd = gptr(level_ptr(J, lm, n));
+        grad = gptr(J->grad);
+    } else {
+        cur = gptr(level_ptr(J, lm, n));
+        prv = gptr(level_ptr(J, lm, n - 1));
+        out = gptr(level_ptr(J, lm, n + 1));
+    }
+    const gfloat *kap = gptr(J->kappa);
+    const float eta_dt = J->eta_dt;
+
+    const int col = tx * TX + lane;
+    const int x = col - M;
+    const bool act = x >= 0 && x < nx;
+    // every neighbour of an active cell lies inside the frame (zeros beyond the
+    // padded grid), where k_step2d reads the same values from LDS and its queue
+    const int64_t p64 = pitch, rz = (int64_t)(z + M) * p64 + col;
+    float o = 0.f, pc = 0.f, kv = 0.f, gv = 0.f, lf = 0.f;
+    if (act) {
+        pc = cur[rz];
+        kv = kap[rz];
+        const float pv = prv[rz];
+        float acc = 0.f;
+#pragma unroll
+        for (int m = M; m > KD; --m) {
+            const float t = (cur[rz + m] + cur[rz - m]) + (cur[rz + m * p64] + cur[rz - m * p64]);
+            acc = fmaf(W.c[m], t, acc);
+        }
+        if constexpr (KD < M) acc = fmaf(W.t2[KD], pc, acc);
+#pragma unroll
+        for (int m = KD; m >= 1; --m) {
+            const float d = ((cur[rz + m] - pc) + (cur[rz - m] - pc)) +
+                            ((cur[rz + m * p64] - pc) + (cur[rz - m * p64] - pc));
+            acc = fmaf(W.c[m], d, acc);
+        }
+        float val = fmaf(kv, acc, 2.f * pc);
+        // the source term rounded as in k_step2d: its product first, then the
+        // sum (never fused into one fma)
+        if (!ADJ && J->src_x == x && J->src_z == z) {
+#pragma clang fp contract(off)
+            const float srcv = J->src_scale * J->wavelet[n];
+            val = val + srcv;
+        }
+        const int dxs = sponge_depth(x, nx, nb), dz = sponge_depth(z, nz, nb);
+        o = leapfrog(val, pv, dxs * dxs + dz * dz, eta_dt);
+        if constexpr (ADJ) {
+            if (accum) {
+                gv = grad[rz];
+                const float fc = fwd[rz];
+#pragma unroll
+                for (int m = M; m > KD; --m) {
+                    const float t = (fwd[rz + m] + fwd[rz - m]) + (fwd[rz + m * p64] + fwd[rz - m * p64]);
+                    lf = fmaf(W.c[m], t, lf);
+                }
+                if constexpr (KD < M) lf = fmaf(W.t2[KD], fc, lf);
+#pragma unroll
+                for (int m = KD; m >= 1; --m) {
+                    const float d = ((fwd[rz + m] - fc) + (fwd[rz - m] - fc)) +
+                                    ((fwd[rz + m * p64] - fc) + (fwd[rz - m * p64] - fc));
+                    lf = fmaf(W.c[m], d, lf);
+                }
+            }
+        }
+    }
+    if constexpr (ADJ) {
+        // receivers on this row: lane i takes the list's i-th, and the sum
+        // reaches the lane of its column through LDS (block-uniform branch)
+        const int rp = J->rt_start[local], re = J->rt_start[local + 1];
+        if (rp < re) {
+            const int idx = rp + lane;
+            const int key = idx < re ? J->rt_key[idx] : -1;
+            const int r = key >= 0 ? J->rt_rec[idx] : -1;
+            sinj[lane] = 0.f;
+            __syncthreads();
+            if (r >= 0) sinj[key & 63] = adj_source(J, n, r);
+            __syncthreads();
+            o += kv * sinj[lane];
+        }
+    }
+    if (act) {
+        out[rz] = o;
+        if constexpr (ADJ) {
+            if (accum) grad[rz] = fmaf(pc, lf, gv);
+        }
+    }
+}
+
 // ------------------------------------------------------------ side kernels
 // kappa' = (v dt/dx)^2 on the padded grid (edge-replicated model), 0 on the frame.
 __global__ void k_prep_kappa(const float *__restrict__ v, float *__restrict__ kappa,
@@ -1263,6 +1402,13 @@ static void launch_step_m(int ndim, int nw, bool adj, const Job *jobs, const int
         case 42: launch_3d<M, 4, 2>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, lm, st); break;
         default: launch_3d<M, 4, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, lm, st); break;
         }
+    } else if (nw == 1) {   // one-row tiles, one cell per lane
+        if (adj)
+            hipLaunchKernelGGL((k_step2d_direct<M, true>), dim3(grid), dim3(64), 0, st, jobs,
+                               prefix, njobs, step, ttiles, remap, lm);
+        else
+            hipLaunchKernelGGL((k_step2d_direct<M, false>), dim3(grid), dim3(64), 0, st, jobs,
+                               prefix, njobs, step, ttiles, remap, lm);
     } else {
         if (adj)
             hipLaunchKernelGGL((k_step2d<M, true>), dim3(grid), dim3(64), 0, st, jobs, prefix,

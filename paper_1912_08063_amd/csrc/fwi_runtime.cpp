@@ -307,6 +307,19 @@ int shape_code(bool adj, int M)
     }
     return adj || M >= 8 ? 42 : 4;
 }
+// 2-D launches: grids too small to fill the GPU take the one-cell-per-lane
+// kernel with one-row tiles (shape code 1), whose launch is one round of load
+// latency; larger ones the marching kernel (code 4), which reads each field
+// once.  The split is by the cells one launch updates (FWI_DIRECT2D=0/1
+// forces either).
+constexpr int64_t kDirect2dCells = 1 << 21;
+bool direct_2d(const Geometry &g, int njobs)
+{
+    if (g.ndim != 2) return false;
+    if (const char *e = getenv("FWI_DIRECT2D")) return atoi(e) != 0;
+    return (int64_t)njobs * g.nz * g.nx <= kDirect2dCells;
+}
+
 int block_waves(int code) { return code == 8 ? 8 : 4; }
 int block_rows(int code) { return code == 42 ? 2 : 4; }
 
@@ -351,6 +364,10 @@ void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *
                 z = zc;
             }
         }
+    } else if (direct_2d(g, njobs)) {
+        *zc = 1;   // one-row tiles of the one-cell-per-lane kernel
+        *nzc = g.nz;
+        return;
     } else {
         // 2-D fields are small and largely cache-resident: many short chunks
         // (16384 blocks: 12-row chunks for 32 shots of 1064 x 360, 8 % faster
@@ -440,6 +457,7 @@ int prepare(Ctx &c, const fwi_problem *p, int mode, const fwi_ckpt *ck, void *ws
     if (const char *e = getenv("FWI_XCD_REMAP")) c.remap = atoi(e) != 0;
     c.nw = shape_code(false, c.g.M);
     c.nw_adj = shape_code(true, c.g.M);
+    if (c.g.ndim == 2) c.nw = c.nw_adj = direct_2d(c.g, p->nshots) ? 1 : 4;
     return FWI_OK;
 }
 

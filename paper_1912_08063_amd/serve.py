@@ -126,7 +126,7 @@ class _Active:
     pass
 
 
-POLICIES = ("srpt", "fifo")
+POLICIES = ("srpt", "srpt_oldest", "fifo")
 
 
 class Server:
@@ -137,6 +137,9 @@ class Server:
     the least remaining work (padded cells x program operations left) while
     their cells stay within fill_cells, so a long job yields the GPU to short
     ones that arrive during it and resumes afterwards.
+    policy "srpt_oldest": as srpt, and the job that arrived first among the
+    resident ones also advances every chunk (its cells outside the fill
+    limit), which bounds how long any job can be paused.
     policy "fifo": requests are admitted in arrival order while their cells
     fit fill_cells, and every admitted job advances each chunk.
     On the full-size request stream at 0.5x to 1.0x the saturated rate, srpt
@@ -285,7 +288,14 @@ class Server:
             _, left = _lib.fwi_job_query(a.handle)
             return (a.req.problem.padded_cells * left, a.req.arrival, a.req.rid)
         chosen, cells = [], 0
-        for a in sorted(active, key=work):
+        rest = active
+        if self.policy == "srpt_oldest":
+            # the longest-waiting job always advances, outside the fill limit:
+            # a long job is never starved by a stream of short ones
+            oldest = min(active, key=lambda a: (a.req.arrival, a.req.rid))
+            chosen.append(oldest)
+            rest = [a for a in active if a is not oldest]
+        for a in sorted(rest, key=work):
             c = a.req.problem.padded_cells
             if chosen and cells + c > self.fill_cells:
                 continue

@@ -37,13 +37,16 @@ def test_gradient_2d(order):
     _check(P, obs, v0, "every:25")
 
 
-def test_gradient_2d_receivers_on_tile_and_chunk_edges(monkeypatch):
+@pytest.mark.parametrize("direct", ["0", "1"])
+def test_gradient_2d_receivers_on_tile_and_chunk_edges(direct, monkeypatch):
     """2-D adjoint steps add the adjoint source themselves, per tile and row:
     a full receiver row (64 cells per tile), cells on both sides of tile and
     row-chunk edges, and a duplicated cell, for two shots.  With nb = 6 and
     an M = 4 frame, model column c is memory column c + 10 (tiles start at
-    multiples of 64) and model row r is padded row r + 6 (chunks of 10 rows)."""
+    multiples of 64) and model row r is padded row r + 6 (chunks of 10 rows).
+    Both 2-D kernels: the marching one and the one-cell-per-lane one."""
     monkeypatch.setenv("FWI_ZCHUNK", "10")
+    monkeypatch.setenv("FWI_DIRECT2D", direct)
     P = wl.small_2d(nz=40, nx=150, nt=120, nb=6, nshots=2, nrec=156)
     rec = [[4, x] for x in range(150)] + [[3, 53], [3, 54], [13, 117], [14, 118], [39, 149],
                                           [3, 53]]
@@ -226,3 +229,19 @@ def test_lbfgs_matches_the_oracle_reference():
     up_g = v.cpu().numpy().astype(np.float64) - v0
     up_r = vr - v0
     assert rel_l2(up_g, up_r) <= 1e-2, rel_l2(up_g, up_r)
+
+
+@pytest.mark.parametrize("order", [8, 16, 2])
+def test_2d_direct_and_marching_kernels_bitwise_equal(order, monkeypatch):
+    """The one-cell-per-lane 2-D kernels (small grids) and the marching ones
+    evaluate the same terms in the same order: traces, misfit and dv of a
+    three-shot gradient (every-13 snapshots, sponge, receivers on tile edges)
+    are bitwise equal."""
+    P, obs, v0 = _setup(wl.small_2d(nz=45, nx=140, nt=150, order=order, nshots=3, nrec=33))
+    P.rec_pos[1, :4] = [[0, 0], [0, 63 - 6], [44, 139], [20, 64 - 6]]
+    out = {}
+    for d in ("0", "1"):
+        monkeypatch.setenv("FWI_DIRECT2D", d)
+        out[d] = gpu_gradient(P, v0, obs, "every:13")
+    (m0, g0, t0), (m1, g1, t1) = out["0"], out["1"]
+    assert np.array_equal(t0, t1) and np.array_equal(g0, g1) and m0 == m1
