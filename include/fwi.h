@@ -276,22 +276,32 @@ typedef struct fwi_job fwi_job;
 
 enum fwi_job_kind { FWI_JOB_FORWARD = 0, FWI_JOB_GRADIENT = 1 };
 
-/* Device bytes one job needs (kind FWI_JOB_*; gradient jobs checkpoint every
- * `chunk` steps).  Host-only. */
-int fwi_job_bytes(const fwi_problem *prob, int32_t kind, int32_t chunk, uint64_t *h_bytes);
+/* Device bytes one job needs (kind FWI_JOB_*).  A gradient job checkpoints
+ * by `ckpt` (FWI_CKPT_EVERY or FWI_CKPT_REVOLVE, as for fwi_gradient), or
+ * every `chunk` steps when ckpt is NULL; forward jobs ignore it.  Host-only.
+ * Errors: FWI_EINVAL for a bad kind, chunk < 1, nshots != 1 or a bad ckpt. */
+int fwi_job_bytes(const fwi_problem *prob, int32_t kind, int32_t chunk, const fwi_ckpt *ckpt,
+                  uint64_t *h_bytes);
 
 /* Validates and stages a job (synchronises `stream`): as fwi_forward (kind
  * FORWARD: traces required) or fwi_gradient (kind GRADIENT: obs and dv
- * required, traces optional), with checkpoints every `chunk` steps.  All
- * arrays, and `mem`, must stay alive until the job is done and the stream has
- * passed its last advance.  *h_job receives a host handle (fwi_job_destroy). */
-int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const float *v,
-                   const float *src, const int32_t *src_pos, const int32_t *rec_pos,
-                   const float *obs, float *traces, float *dv, void *mem, uint64_t mem_bytes,
-                   void *stream, fwi_job **h_job);
+ * required, traces optional) with the checkpoint policy `ckpt` (NULL: every
+ * `chunk` steps).  The job's traces, misfit and gradient are bitwise those of
+ * the stand-alone call with the same policy.  A binomial (revolve) job moves
+ * between forward recomputation and adjoint steps within one chunk; its
+ * snapshots are copies of two consecutive levels, and a restore copies them
+ * back into the two-level ring.  All arrays, and `mem`, must stay alive until the job is
+ * done and the stream has passed its last advance.  *h_job receives a host
+ * handle (fwi_job_destroy). */
+int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const fwi_ckpt *ckpt,
+                   const float *v, const float *src, const int32_t *src_pos,
+                   const int32_t *rec_pos, const float *obs, float *traces, float *dv, void *mem,
+                   uint64_t mem_bytes, void *stream, fwi_job **h_job);
 
-/* Workspace (device, 256-byte aligned) of one fwi_jobs_advance over njobs jobs. */
-int fwi_jobs_ws_bytes(int32_t njobs, uint64_t *h_bytes);
+/* Workspace (device, 256-byte aligned) of one fwi_jobs_advance over up to
+ * njobs jobs and ksteps steps (launch tables and per-step level lists).
+ * Host-only.  Errors: FWI_EINVAL for njobs < 0, ksteps < 1 or NULL output. */
+int fwi_jobs_ws_bytes(int32_t njobs, int32_t ksteps, uint64_t *h_bytes);
 
 /* Advances every job by up to ksteps steps of its current phase, in shared
  * launches on `stream`, and enqueues the per-job operations due around them
@@ -299,13 +309,17 @@ int fwi_jobs_ws_bytes(int32_t njobs, uint64_t *h_bytes);
  * skipped.  Does not synchronise: the launch tables reach the device as
  * kernel arguments of a small assembly kernel that writes them into `ws`, so
  * a caller can enqueue the next chunk while this one runs.  `ws` may be
- * reused by the next call on the same stream (stream order protects it). */
+ * reused by the next call on the same stream (stream order protects it).
+ * Errors: FWI_EINVAL for njobs < 0, ksteps < 1 or a NULL job; FWI_ENOMEM if
+ * ws_bytes is below fwi_jobs_ws_bytes(njobs, ksteps). */
 int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *ws,
                      uint64_t ws_bytes, void *stream);
 
 /* Host-side state: *h_done = 1 once all of the job's work has been enqueued
- * (results are valid after the stream has finished it). */
-int fwi_job_query(const fwi_job *job, int32_t *h_done, int64_t *h_ops_left);
+ * (results are valid after the stream has finished it); *h_steps_left (if
+ * not NULL) = the time steps, forward, recomputation and adjoint, still to
+ * enqueue.  Host-only. */
+int fwi_job_query(const fwi_job *job, int32_t *h_done, int64_t *h_steps_left);
 
 /* Misfit of a finished gradient job (synchronises `stream`). */
 int fwi_job_misfit(const fwi_job *job, double *h_misfit, void *stream);

@@ -80,10 +80,10 @@ def load():
     lib.fwi_velocity_range.argtypes = [vp, i64, P(ctypes.c_float), P(ctypes.c_float), vp, u64,
                                        vp]
     lib.fwi_stream_probe.argtypes = [vp, vp, vp, vp, i64, i32, vp]
-    lib.fwi_job_bytes.argtypes = [prob, i32, i32, P(u64)]
-    lib.fwi_job_create.argtypes = [prob, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp,
+    lib.fwi_job_bytes.argtypes = [prob, i32, i32, ck, P(u64)]
+    lib.fwi_job_create.argtypes = [prob, i32, i32, ck, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp,
                                    P(vp)]
-    lib.fwi_jobs_ws_bytes.argtypes = [i32, P(u64)]
+    lib.fwi_jobs_ws_bytes.argtypes = [i32, i32, P(u64)]
     lib.fwi_jobs_advance.argtypes = [P(vp), i32, i32, vp, u64, vp]
     lib.fwi_job_query.argtypes = [vp, P(i32), P(i64)]
     lib.fwi_job_misfit.argtypes = [vp, P(ctypes.c_double), vp]
@@ -202,25 +202,27 @@ def fwi_stream_probe(a, b, c, out, n, variant, stream):
     _check(load().fwi_stream_probe(a, b, c, out, n, variant, stream), "fwi_stream_probe")
 
 
-def fwi_job_bytes(prob, kind, chunk):
+def fwi_job_bytes(prob, kind, chunk, ckpt=None):
     out = ctypes.c_uint64()
-    _check(load().fwi_job_bytes(ctypes.byref(prob), kind, chunk, ctypes.byref(out)),
-           "fwi_job_bytes")
+    _check(load().fwi_job_bytes(ctypes.byref(prob), kind, chunk,
+                                ctypes.byref(ckpt) if ckpt is not None else None,
+                                ctypes.byref(out)), "fwi_job_bytes")
     return out.value
 
 
-def fwi_job_create(prob, kind, chunk, v, src, src_pos, rec_pos, obs, traces, dv, mem,
+def fwi_job_create(prob, kind, chunk, ckpt, v, src, src_pos, rec_pos, obs, traces, dv, mem,
                    mem_bytes, stream):
     h = ctypes.c_void_p()
-    _check(load().fwi_job_create(ctypes.byref(prob), kind, chunk, v, src, src_pos, rec_pos,
-                                 obs, traces, dv, mem, mem_bytes, stream, ctypes.byref(h)),
-           "fwi_job_create")
+    _check(load().fwi_job_create(ctypes.byref(prob), kind, chunk,
+                                 ctypes.byref(ckpt) if ckpt is not None else None, v, src,
+                                 src_pos, rec_pos, obs, traces, dv, mem, mem_bytes, stream,
+                                 ctypes.byref(h)), "fwi_job_create")
     return h
 
 
-def fwi_jobs_ws_bytes(njobs):
+def fwi_jobs_ws_bytes(njobs, ksteps):
     out = ctypes.c_uint64()
-    _check(load().fwi_jobs_ws_bytes(njobs, ctypes.byref(out)), "fwi_jobs_ws_bytes")
+    _check(load().fwi_jobs_ws_bytes(njobs, ksteps, ctypes.byref(out)), "fwi_jobs_ws_bytes")
     return out.value
 
 

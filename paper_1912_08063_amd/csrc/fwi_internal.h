@@ -82,6 +82,8 @@ struct Job {
     const int32_t *rt_key;     // [receiver cells]
     float *traces;         // [nt][nrec]
     const float *res;      // [nt][nrec] adjoint source
+    // per-round time levels of a serving chunk (nullptr: n0 + step / k0 - step)
+    const int32_t *lev;
 };
 
 // Forward levels that a launch finds in the snapshot store instead of the
@@ -99,16 +101,22 @@ struct LevelMap {
 // each entry is copied from the job's own table entry in its memory and its
 // time window for this chunk is patched in.  Passed by value as a kernel
 // argument, so the host neither copies tables nor waits for the stream.
-constexpr int kAssembleJobs = 32;
-constexpr int kAssemblePrefix = 96;
+constexpr int kAssembleJobs = 16;
+constexpr int kAssemblePrefix = 64;
+constexpr int kAssembleLevels = 384;
 struct AssembleArgs {
     int32_t count;                  // entries first .. first + count - 1
     int32_t first;
     int32_t nprefix;                // prefix ints pfirst .. pfirst + nprefix - 1
     int32_t pfirst;
+    int32_t nlev;                   // level-list ints lfirst .. lfirst + nlev - 1
+    int32_t lfirst;
     const Job *src[kAssembleJobs];  // the job's own table entry (device)
     int32_t win[kAssembleJobs][7];  // n0, k0, fwd_lo, fwd_hi, adj_lo, adj_hi, record
+    int32_t levoff[kAssembleJobs];  // entry's level list in the group's lists (-1: none)
     int32_t prefix[kAssemblePrefix];
+    int32_t lev[kAssembleLevels];
 };
+static_assert(sizeof(AssembleArgs) <= 4000, "kernel arguments are limited to 4 KB");
 
 }  // namespace fwi

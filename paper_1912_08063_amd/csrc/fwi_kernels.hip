@@ -106,6 +106,16 @@ __device__ __forceinline__ int xcd_remap(int b, int T)
 
 __device__ __forceinline__ int mod_pos(int a, int R) { int m = a % R; return m < 0 ? m + R : m; }
 
+// Time level a launch's step updates for job J: n0 + step (forward) or
+// k0 - step (adjoint), or, for jobs that change direction within a chunk
+// (binomial checkpointing in the serving path), the step's entry of the job's
+// level list (kNoLevel: no step of this launch's direction in that round).
+__device__ __forceinline__ int step_level(const Job *__restrict__ J, int step, bool adj)
+{
+    if (J->lev) return J->lev[step];
+    return adj ? J->k0 - step : J->n0 + step;
+}
+
 // Field of forward level L: the ring slot L mod R, or a snapshot field the
 // level map names (block-uniform, scalar).
 __device__ __forceinline__ float *level_ptr(const Job *__restrict__ J, const LevelMap &lm, int L)
@@ -258,13 +268,13 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         const int gb = b - ttiles;
         const int j = find_job(prefix + njobs + 1, njobs, gb);
         const Job *J = jobs + j;
-        gather_block(J, lm, (gb - prefix[njobs + 1 + j]) * blockDim.x + tid, J->n0 + step);
+        gather_block(J, lm, (gb - prefix[njobs + 1 + j]) * blockDim.x + tid, step_level(J, step, false));
         return;
     }
     if (remap) b = xcd_remap(b, ttiles);
     const int j = find_job(prefix, njobs, b);
     const Job *__restrict__ J = jobs + j;
-    const int n = ADJ ? J->k0 - step : J->n0 + step;
+    const int n = step_level(J, step, ADJ);
     if (ADJ ? (n < J->adj_lo || n >= J->adj_hi) : (n < J->fwd_lo || n >= J->fwd_hi)) return;
 
     const int nz = J->nz, ny = J->ny, nx = J->nx, pitch = J->pitch, nb = J->nb;
@@ -614,13 +624,13 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
         const int gb = b - ttiles;
         const int j = find_job(prefix + njobs + 1, njobs, gb);
         const Job *J = jobs + j;
-        gather_block(J, lm, (gb - prefix[njobs + 1 + j]) * blockDim.x + lane, J->n0 + step);
+        gather_block(J, lm, (gb - prefix[njobs + 1 + j]) * blockDim.x + lane, step_level(J, step, false));
         return;
     }
     if (remap) b = xcd_remap(b, ttiles);
     const int j = find_job(prefix, njobs, b);
     const Job *__restrict__ J = jobs + j;
-    const int n = ADJ ? J->k0 - step : J->n0 + step;
+    const int n = step_level(J, step, ADJ);
     if (ADJ ? (n < J->adj_lo || n >= J->adj_hi) : (n < J->fwd_lo || n >= J->fwd_hi)) return;
 
     const int nz = J->nz, nx = J->nx, pitch = J->pitch, nb = J->nb;
@@ -817,13 +827,13 @@ __global__ __launch_bounds__(64) void k_step2d_direct(const Job *__restrict__ jo
         const int gb = b - ttiles;
         const int j = find_job(prefix + njobs + 1, njobs, gb);
         const Job *J = jobs + j;
-        gather_block(J, lm, (gb - prefix[njobs + 1 + j]) * blockDim.x + lane, J->n0 + step);
+        gather_block(J, lm, (gb - prefix[njobs + 1 + j]) * blockDim.x + lane, step_level(J, step, false));
         return;
     }
     if (remap) b = xcd_remap(b, ttiles);
     const int j = find_job(prefix, njobs, b);
     const Job *__restrict__ J = jobs + j;
-    const int n = ADJ ? J->k0 - step : J->n0 + step;
+    const int n = step_level(J, step, ADJ);
     if (ADJ ? (n < J->adj_lo || n >= J->adj_hi) : (n < J->fwd_lo || n >= J->fwd_hi)) return;
 
     const int nz = J->nz, nx = J->nx, pitch = J->pitch, nb = J->nb;
@@ -1003,7 +1013,7 @@ __global__ void k_adj_inject(const Job *__restrict__ jobs, const int *__restrict
 {
     const int j = find_job(gprefix, njobs, blockIdx.x);
     const Job *J = jobs + j;
-    const int k = J->k0 - step;
+    const int k = step_level(J, step, true);
     const int r = (blockIdx.x - gprefix[j]) * blockDim.x + threadIdx.x;
     if (k < J->adj_lo || k >= J->adj_hi || r >= J->nrec || !J->rec_head[r]) return;
     const float s = adj_source(J, k, r);
@@ -1224,10 +1234,11 @@ void launch_stream_probe(const float *a, const float *b, const float *c, float *
 }
 
 // Launch tables of a serving chunk (see AssembleArgs): block i copies entry
-// i from the job's memory and patches its time window; block 0 also writes
-// the launch's slice of the prefix arrays.
+// i from the job's memory and patches its time window and level list; block
+// 0 also writes the launch's slices of the prefix arrays and level lists.
 __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a, Job *__restrict__ table,
-                                                 int *__restrict__ prefix)
+                                                 int *__restrict__ prefix,
+                                                 int32_t *__restrict__ levels)
 {
     const int i = blockIdx.x;
     if (i < a.count) {
@@ -1245,10 +1256,13 @@ __global__ __launch_bounds__(64) void k_assemble(AssembleArgs a, Job *__restrict
             J.adj_lo = a.win[i][4];
             J.adj_hi = a.win[i][5];
             J.record = a.win[i][6];
+            J.lev = a.levoff[i] >= 0 ? levels + a.levoff[i] : nullptr;
         }
     }
-    if (i == 0)
+    if (i == 0) {
         for (int p = threadIdx.x; p < a.nprefix; p += blockDim.x) prefix[a.pfirst + p] = a.prefix[p];
+        for (int p = threadIdx.x; p < a.nlev; p += blockDim.x) levels[a.lfirst + p] = a.lev[p];
+    }
 }
 
 // Non-finite cells of forward level L of every job (ring slot L mod R):
@@ -1307,10 +1321,11 @@ int scratch_address(void **ptr)
 // ---------------------------------------------------------------- launchers
 int vstats_blocks() { return 256; }
 
-void launch_assemble(const AssembleArgs &a, Job *table, int *prefix, hipStream_t st)
+void launch_assemble(const AssembleArgs &a, Job *table, int *prefix, int32_t *levels,
+                     hipStream_t st)
 {
     hipLaunchKernelGGL(k_assemble, dim3(a.count > 0 ? a.count : 1), dim3(64), 0, st, a, table,
-                       prefix);
+                       prefix, levels);
 }
 
 void launch_nonfinite_level(const Job *jobs, int njobs, int L, float *partial, hipStream_t st)

@@ -46,7 +46,8 @@ int vstats_blocks();
 int step_blocks_per_cu(int ndim, int M, int nw, bool adj);
 void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st);
 void launch_nonfinite_level(const Job *jobs, int njobs, int L, float *partial, hipStream_t st);
-void launch_assemble(const AssembleArgs &a, Job *table, int *prefix, hipStream_t st);
+void launch_assemble(const AssembleArgs &a, Job *table, int *prefix, int32_t *levels,
+                     hipStream_t st);
 int scratch_address(void **ptr);
 void launch_stream_probe(const float *a, const float *b, const float *c, float *o, int64_t n,
                          int variant, hipStream_t st);
@@ -1014,6 +1015,9 @@ struct fwi_job {
     Ctx c;
     int kind = 0;
     int chunk = 0;
+    // binomial checkpointing: the job changes direction within a chunk, so
+    // its steps carry per-round levels (Job::lev) instead of one window
+    bool rounds = false;
     std::vector<JobOp> ops;
     size_t head = 0;
     const float *v = nullptr, *obs = nullptr;
@@ -1063,26 +1067,84 @@ int run_immediates(fwi_job *J)
     return FWI_OK;
 }
 
+// Revolve program, with copies: snapshots copy two levels out of the two-level
+// ring and restores copy them back (the launch-wide level maps of the
+// lockstep path do not apply to jobs that share launches).  The order of
+// operations is that of forward_phase / backward_phase.
+void build_revolve_program(fwi_job *J)
+{
+    const int nt = J->prob.nt;
+    const bool rec = J->prob.nrec > 0;
+    std::vector<JobOp> &ops = J->ops;
+    const std::vector<Action> acts = revolve_schedule(nt, J->c.po.nsnap, nullptr);
+    std::vector<int> slot_time(std::max(J->c.po.nsnap, 1), -1);
+    auto fwd = [&](int a, int b, int record) {
+        if (a < b) ops.push_back(JobOp{JOP_FWD, a, b, 0, record});
+    };
+    int cur = 0;
+    size_t i = 0;
+    for (; i < acts.size() && acts[i].op != OP_ADJOINT; ++i) {   // recording sweep
+        const Action &a = acts[i];
+        if (a.op == OP_ADVANCE) {
+            fwd(cur, a.arg, 1);
+            cur = a.arg;
+        } else if (a.op == OP_TAKESHOT) {
+            ops.push_back(JobOp{JOP_SNAP, cur, 0, a.arg, 0});
+            slot_time[a.arg] = cur;
+        }
+    }
+    fwd(cur, nt, 1);
+    if (rec) ops.push_back(JobOp{JOP_GATHER, nt, 0, 0, 0});
+    ops.push_back(JobOp{JOP_MISFIT, 0, 0, 0, 0});
+    ops.push_back(JobOp{JOP_ZERO_ADJ, 0, 0, 0, 0});
+    ops.push_back(JobOp{JOP_ADJ, nt, nt, 0, 0});
+    cur = nt;
+    for (; i < acts.size(); ++i) {   // reversal
+        const Action &a = acts[i];
+        switch (a.op) {
+        case OP_ADJOINT: ops.push_back(JobOp{JOP_ADJ, a.arg, a.arg, 0, 0}); break;
+        case OP_ADVANCE: fwd(cur, a.arg, 0); cur = a.arg; break;
+        case OP_TAKESHOT:
+            ops.push_back(JobOp{JOP_SNAP, cur, 0, a.arg, 0});
+            slot_time[a.arg] = cur;
+            break;
+        case OP_RESTORE:
+            cur = slot_time[a.arg];
+            ops.push_back(JobOp{JOP_RESTORE, cur, 0, a.arg, 0});
+            break;
+        case OP_RESTART: ops.push_back(JobOp{JOP_ZERO_STATE, 0, 0, 0, 0}); cur = 0; break;
+        default: break;
+        }
+    }
+    ops.push_back(JobOp{JOP_FOLD, 0, 0, 0, 0});
+}
+
+// Program of a job: step ranges (split into chunks by fwi_jobs_advance) and
+// the per-job operations between them, for the job's checkpoint policy.
 void build_program(fwi_job *J)
 {
-    const int nt = J->prob.nt, K = J->chunk;
+    const int nt = J->prob.nt;
     const bool rec = J->prob.nrec > 0;
     std::vector<JobOp> &ops = J->ops;
     auto fwd = [&](int a, int b, int record) {
-        for (int s = a; s < b; s += K) ops.push_back(JobOp{JOP_FWD, s, std::min(b, s + K), 0, record});
+        if (a < b) ops.push_back(JobOp{JOP_FWD, a, b, 0, record});
     };
     auto adj = [&](int hi, int lo) {
-        for (int s = hi; s >= lo; s -= K) ops.push_back(JobOp{JOP_ADJ, s, std::max(lo, s - K + 1), 0, 0});
+        if (hi >= lo) ops.push_back(JobOp{JOP_ADJ, hi, lo, 0, 0});
     };
     if (J->kind == 0) {   // forward
         fwd(0, nt, 1);
         if (rec) ops.push_back(JobOp{JOP_GATHER, nt, 0, 0, 0});
         return;
     }
-    const int ctop = J->c.po.ctop;
+    if (J->c.po.kind == FWI_CKPT_REVOLVE) {
+        build_revolve_program(J);
+        return;
+    }
+    const int K = J->c.po.every, ctop = J->c.po.ctop;
     for (int s = 0; s < nt; s += K) {
         const int e = std::min(nt, s + K);
-        ops.push_back(JobOp{JOP_FWD, s, e, 0, 1});
+        fwd(s, e, 1);
         if (e % K == 0 && e <= ctop - K) ops.push_back(JobOp{JOP_SNAP, e, 0, e / K - 1, 0});
     }
     if (rec) ops.push_back(JobOp{JOP_GATHER, nt, 0, 0, 0});
@@ -1367,22 +1429,31 @@ int fwi_revolve_plan(int32_t nsteps, int32_t slots, int32_t *h_ops, int64_t cap,
     }
 }
 
-int fwi_job_bytes(const fwi_problem *prob, int32_t kind, int32_t chunk, uint64_t *h_bytes)
+// Checkpoint policy of a gradient job: as given, or every `chunk` steps.
+fwi_ckpt job_ckpt(int32_t chunk, const fwi_ckpt *ckpt)
+{
+    if (ckpt) return *ckpt;
+    fwi_ckpt ck{};
+    ck.kind = FWI_CKPT_EVERY;
+    ck.every = chunk;
+    return ck;
+}
+
+int fwi_job_bytes(const fwi_problem *prob, int32_t kind, int32_t chunk, const fwi_ckpt *ckpt,
+                  uint64_t *h_bytes)
 {
     if (kind != FWI_JOB_FORWARD && kind != FWI_JOB_GRADIENT) return fail(FWI_EINVAL, "bad job kind");
     if (chunk < 1) return fail(FWI_EINVAL, "chunk must be >= 1");
     if (prob && prob->nshots != 1) return fail(FWI_EINVAL, "a job is one shot");
-    fwi_ckpt ck{};
-    ck.kind = FWI_CKPT_EVERY;
-    ck.every = chunk;
+    const fwi_ckpt ck = job_ckpt(chunk, ckpt);
     return fwi_workspace_bytes(prob, kind == FWI_JOB_FORWARD ? FWI_MODE_FORWARD : FWI_MODE_GRADIENT,
                                &ck, h_bytes);
 }
 
-int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const float *v,
-                   const float *src, const int32_t *src_pos, const int32_t *rec_pos,
-                   const float *obs, float *traces, float *dv, void *mem, uint64_t mem_bytes,
-                   void *stream, fwi_job **h_job)
+int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const fwi_ckpt *ckpt,
+                   const float *v, const float *src, const int32_t *src_pos,
+                   const int32_t *rec_pos, const float *obs, float *traces, float *dv,
+                   void *mem, uint64_t mem_bytes, void *stream, fwi_job **h_job)
 {
     if (!h_job) return fail(FWI_EINVAL, "NULL output");
     *h_job = nullptr;
@@ -1394,9 +1465,7 @@ int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const f
         J->prob = *prob;
         J->kind = kind;
         J->chunk = chunk;
-        fwi_ckpt ck{};
-        ck.kind = FWI_CKPT_EVERY;
-        ck.every = chunk;
+        const fwi_ckpt ck = job_ckpt(chunk, ckpt);
         const int mode = kind == FWI_JOB_FORWARD ? FWI_MODE_FORWARD : FWI_MODE_GRADIENT;
         Ctx &c = J->c;
         int st = prepare(c, &J->prob, mode, &ck, mem, mem_bytes, nullptr, 0, stream);
@@ -1419,6 +1488,7 @@ int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const f
         if (st) return st;
         zero(c.jobs[0].ring, (uint64_t)c.g.fstride * c.po.R, c.st);
         HIP_TRY(hipGetLastError());
+        J->rounds = kind == FWI_JOB_GRADIENT && c.po.kind == FWI_CKPT_REVOLVE;
         build_program(J.get());
         *h_job = J.release();
         return FWI_OK;
@@ -1429,22 +1499,81 @@ int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const f
     }
 }
 
-int fwi_jobs_ws_bytes(int32_t njobs, uint64_t *h_bytes)
+// Launch groups of one advance: one per (dimension, order, direction, block
+// shape); 2-D jobs use two shapes, so at most 4 orders x 2 directions x
+// (2 + 1) = 24 groups.
+constexpr int kMaxGroups = 24;
+
+int fwi_jobs_ws_bytes(int32_t njobs, int32_t ksteps, uint64_t *h_bytes)
 {
-    if (njobs < 0 || !h_bytes) return fail(FWI_EINVAL, "bad argument");
-    // at most 16 launch groups (2-D/3-D x forward/adjoint x 4 orders), each a
-    // job table and two prefix arrays
-    *h_bytes = 16 * (align_up(sizeof(Job) * (uint64_t)njobs, kAlign) +
-                    align_up(sizeof(int) * 2ull * (njobs + 1), kAlign)) + kAlign;
+    if (njobs < 0 || ksteps < 1 || !h_bytes) return fail(FWI_EINVAL, "bad argument");
+    // per group: a job table, two prefix arrays and the level lists of the
+    // jobs stepping by rounds (at most one per job and group, ksteps each)
+    *h_bytes = kMaxGroups * (align_up(sizeof(Job) * (uint64_t)njobs, kAlign) +
+                             align_up(sizeof(int) * 2ull * (njobs + 1), kAlign) +
+                             align_up(sizeof(int32_t) * (uint64_t)njobs * ksteps, kAlign)) +
+               kAlign;
     return FWI_OK;
 }
+
+namespace {
+
+// One job's part of a chunk when it steps by rounds: the direction and level
+// of its step in each round (0: none, 1: forward, 2: adjoint), the per-job
+// operations due before each round (before[ksteps]: after the last), and
+// whether its forward steps record traces.
+struct RoundPlan {
+    std::vector<int> dir, lev;
+    std::vector<std::vector<JobOp>> before;
+    int record = -1;
+    int used = 0;
+};
+
+// Takes up to ksteps steps from the head of J's program, the operations
+// between them and the ones right after.  Stops early where the recording
+// flag of its forward steps changes (one flag per launch entry).
+void plan_rounds(fwi_job *J, int ksteps, RoundPlan &P)
+{
+    P.dir.assign(ksteps, 0);
+    P.lev.assign(ksteps, kNoLevel);
+    P.before.assign(ksteps + 1, {});
+    int j = 0;
+    while (J->head < J->ops.size()) {
+        JobOp &o = J->ops[J->head];
+        if (!is_step(o)) {
+            P.before[j].push_back(o);
+            ++J->head;
+            continue;
+        }
+        if (j == ksteps) break;
+        if (o.type == JOP_FWD) {
+            const int rec = o.record ? 1 : 0;
+            if (P.record >= 0 && rec != P.record) break;
+            P.record = rec;
+            while (o.a < o.b && j < ksteps) { P.dir[j] = 1; P.lev[j] = o.a++; ++j; }
+            if (o.a >= o.b) ++J->head;
+        } else {
+            while (o.a >= o.b && j < ksteps) { P.dir[j] = 2; P.lev[j] = o.a--; ++j; }
+            if (o.a < o.b) ++J->head;
+        }
+    }
+    P.used = j;
+}
+
+int run_ops(fwi_job *J, const std::vector<JobOp> &ops)
+{
+    for (const JobOp &o : ops) TRY(run_immediate(J, o));
+    return FWI_OK;
+}
+
+}  // namespace
 
 int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *ws,
                      uint64_t ws_bytes, void *stream)
 {
     if (njobs < 0 || (njobs > 0 && !jobs) || ksteps < 1) return fail(FWI_EINVAL, "bad argument");
     uint64_t need = 0;
-    fwi_jobs_ws_bytes(njobs, &need);
+    fwi_jobs_ws_bytes(njobs, ksteps, &need);
     if (!ws || ws_bytes < need) return fail(FWI_ENOMEM, "advance workspace too small");
     if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0)
         return fail(FWI_EINVAL, "workspace must be 256-byte aligned");
@@ -1454,19 +1583,24 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
             if (!jobs[i]) return fail(FWI_EINVAL, "NULL job");
             jobs[i]->c.st = st;
         }
-        // 1. operations due before this chunk's steps
-        for (int i = 0; i < njobs; ++i) TRY(run_immediates(jobs[i]));
-        // 2. gather this chunk's step ranges into launch groups
+        // 1. operations due before this chunk's steps (jobs stepping by
+        // rounds run theirs from their round plan)
+        for (int i = 0; i < njobs; ++i)
+            if (!jobs[i]->rounds) TRY(run_immediates(jobs[i]));
+        // 2. gather this chunk's steps into launch groups
         struct Entry {
             const Job *src;   // the job's own table entry (device)
             int32_t win[7];   // n0, k0, fwd_lo, fwd_hi, adj_lo, adj_hi, record
+            int levoff;       // level list in the group's lists (-1: none)
         };
         struct Group {
             int ndim = 0, M = 0, adj = 0, nw = 4, steps = 0;
             std::vector<Entry> table;
             std::vector<int> tp{0}, gp{0};
+            std::vector<int32_t> lev;   // level lists, ksteps per entry that has one
             Job *d_jobs = nullptr;
             int *d_prefix = nullptr;
+            int32_t *d_lev = nullptr;
             int gthreads = 64;
         };
         std::vector<Group> groups;
@@ -1478,12 +1612,45 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
             g.ndim = ndim; g.M = M; g.adj = adj; g.nw = nw;
             return g;
         };
+        auto add = [&](fwi_job *J, bool isadj, const Entry &e, int steps, bool record,
+                       const int32_t *lev) {
+            const Job &t = J->c.jobs[0];
+            Group &g = group_of(J->c.g.ndim, J->c.g.M, isadj, isadj ? J->c.nw_adj : J->c.nw);
+            g.steps = std::max(g.steps, steps);
+            g.gthreads = J->c.gthreads;
+            Entry x = e;
+            if (lev) {
+                x.levoff = (int)g.lev.size();
+                g.lev.insert(g.lev.end(), lev, lev + ksteps);
+            }
+            g.table.push_back(x);
+            g.tp.push_back(g.tp.back() + t.tile[isadj ? 1 : 0].ntiles);
+            g.gp.push_back(g.gp.back() + ((!isadj && record) || isadj ? t.ngather : 0));
+        };
+        std::vector<RoundPlan> plans(njobs);
         for (int i = 0; i < njobs; ++i) {
             fwi_job *J = jobs[i];
+            const Job &t = J->c.jobs[0];
+            if (J->rounds) {
+                RoundPlan &P = plans[i];
+                plan_rounds(J, ksteps, P);
+                const bool record = P.record == 1 && J->rec;
+                for (int d = 1; d <= 2; ++d) {
+                    std::vector<int32_t> lev(ksteps, kNoLevel);
+                    int last = 0;
+                    for (int j = 0; j < P.used; ++j)
+                        if (P.dir[j] == d) { lev[j] = P.lev[j]; last = j + 1; }
+                    if (!last) continue;
+                    Entry e{J->c.d_jobs, {0, 0, 0, J->prob.nt, 1, J->prob.nt + 1,
+                                          d == 1 && record ? 1 : 0}, -1};
+                    add(J, d == 2, e, last, d == 1 && record, lev.data());
+                }
+                continue;
+            }
             if (J->head >= J->ops.size()) continue;
             JobOp &o = J->ops[J->head];
-            const Job &t = J->c.jobs[0];
-            Entry e{J->c.d_jobs, {t.n0, t.k0, t.fwd_lo, t.fwd_hi, t.adj_lo, t.adj_hi, t.record}};
+            Entry e{J->c.d_jobs, {t.n0, t.k0, t.fwd_lo, t.fwd_hi, t.adj_lo, t.adj_hi, t.record},
+                    -1};
             int steps;
             bool record = false;
             if (o.type == JOP_FWD) {
@@ -1503,15 +1670,9 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
             }
             const bool finished = o.type == JOP_FWD ? o.a >= o.b : o.a < o.b;
             if (finished) ++J->head;
-            const bool isadj = o.type == JOP_ADJ;
-            Group &g = group_of(J->c.g.ndim, J->c.g.M, isadj, isadj ? J->c.nw_adj : J->c.nw);
-            g.steps = std::max(g.steps, steps);
-            g.gthreads = J->c.gthreads;
-            g.table.push_back(e);
-            g.tp.push_back(g.tp.back() + t.tile[isadj ? 1 : 0].ntiles);
-            g.gp.push_back(g.gp.back() + ((o.type == JOP_FWD && record) || o.type == JOP_ADJ
-                                              ? t.ngather : 0));
+            add(J, o.type == JOP_ADJ, e, steps, record, nullptr);
         }
+        if ((int)groups.size() > kMaxGroups) return fail(FWI_EINVAL, "internal: too many launch groups");
         // 3. assemble the tables on the device (kernel arguments carry them:
         // no host copy to wait for; the stream orders them after the previous
         // chunk's launches, which read the same workspace) and launch every
@@ -1524,27 +1685,39 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
             off += align_up(sizeof(Job) * (uint64_t)n, kAlign);
             g.d_prefix = reinterpret_cast<int *>(w + off);
             off += align_up(sizeof(int) * 2ull * (n + 1), kAlign);
+            g.d_lev = reinterpret_cast<int32_t *>(w + off);
+            off += align_up(sizeof(int32_t) * g.lev.size(), kAlign);
+            if (off > ws_bytes) return fail(FWI_EINVAL, "internal: advance workspace layout");
             std::vector<int> pre(g.tp);
             pre.insert(pre.end(), g.gp.begin(), g.gp.end());
-            const int np = (int)pre.size();
-            for (int j0 = 0, p0 = 0; j0 < n || p0 < np;) {
+            const int np = (int)pre.size(), nl = (int)g.lev.size();
+            for (int j0 = 0, p0 = 0, l0 = 0; j0 < n || p0 < np || l0 < nl;) {
                 AssembleArgs a{};
                 a.first = j0;
                 a.count = std::min(kAssembleJobs, n - j0);
                 for (int k = 0; k < a.count; ++k) {
                     a.src[k] = g.table[j0 + k].src;
                     std::copy(g.table[j0 + k].win, g.table[j0 + k].win + 7, a.win[k]);
+                    a.levoff[k] = g.table[j0 + k].levoff;
                 }
                 a.pfirst = p0;
                 a.nprefix = std::min(kAssemblePrefix, np - p0);
                 std::copy(pre.begin() + p0, pre.begin() + p0 + a.nprefix, a.prefix);
-                launch_assemble(a, g.d_jobs, g.d_prefix, st);
+                a.lfirst = l0;
+                a.nlev = std::min(kAssembleLevels, nl - l0);
+                std::copy(g.lev.begin() + l0, g.lev.begin() + l0 + a.nlev, a.lev);
+                launch_assemble(a, g.d_jobs, g.d_prefix, g.d_lev, st);
                 j0 += a.count;
                 p0 += a.nprefix;
+                l0 += a.nlev;
             }
         }
         HIP_TRY(hipGetLastError());
         for (int j = 0; j < ksteps; ++j) {
+            // per-job operations between this job's rounds (snapshot and
+            // restore copies of binomial checkpointing), in stream order
+            for (int i = 0; i < njobs; ++i)
+                if (jobs[i]->rounds) TRY(run_ops(jobs[i], plans[i].before[j]));
             for (Group &g : groups) {
                 if (j >= g.steps) continue;
                 const int n = (int)g.table.size();
@@ -1557,7 +1730,10 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
         }
         HIP_TRY(hipGetLastError());
         // 4. operations due right after this chunk (final gather, residual, fold)
-        for (int i = 0; i < njobs; ++i) TRY(run_immediates(jobs[i]));
+        for (int i = 0; i < njobs; ++i) {
+            if (jobs[i]->rounds) TRY(run_ops(jobs[i], plans[i].before[ksteps]));
+            else TRY(run_immediates(jobs[i]));
+        }
         HIP_TRY(hipGetLastError());
         return FWI_OK;
     } catch (const std::bad_alloc &) {
@@ -1567,12 +1743,17 @@ int fwi_jobs_advance(fwi_job *const *jobs, int32_t njobs, int32_t ksteps, void *
     }
 }
 
-int fwi_job_query(const fwi_job *job, int32_t *h_done, int64_t *h_ops_left)
+int fwi_job_query(const fwi_job *job, int32_t *h_done, int64_t *h_steps_left)
 {
     if (!job) return fail(FWI_EINVAL, "NULL job");
-    const int64_t left = (int64_t)job->ops.size() - (int64_t)job->head;
-    if (h_done) *h_done = left == 0;
-    if (h_ops_left) *h_ops_left = left;
+    int64_t steps = 0;
+    for (size_t i = job->head; i < job->ops.size(); ++i) {
+        const JobOp &o = job->ops[i];
+        if (o.type == JOP_FWD) steps += std::max(0, o.b - o.a);
+        else if (o.type == JOP_ADJ) steps += std::max(0, o.a - o.b + 1);
+    }
+    if (h_done) *h_done = job->head == job->ops.size();
+    if (h_steps_left) *h_steps_left = steps;
     return FWI_OK;
 }
 

@@ -38,6 +38,7 @@ class Request:
     arrival: float                 # seconds after the stream starts
     problem: wl.Problem            # one shot
     obs: Optional[np.ndarray] = None   # gradient: observed traces [1][nt][R]
+    ckpt: Optional[str] = None     # gradient: checkpoint spec (None: the server's)
 
 
 @dataclasses.dataclass
@@ -51,7 +52,7 @@ class Result:
     dv: Optional[np.ndarray] = None
     misfit: Optional[float] = None
     seq: int = -1                  # completion index within the run
-    work: int = 0                  # padded cells x program operations, at admission
+    work: int = 0                  # padded cells x time steps, at admission
     error: Optional[str] = None    # set when the request was refused or failed
 
     @property
@@ -134,7 +135,7 @@ class Server:
 
     policy "srpt": every arrived request that fits the memory budget is
     admitted and stays resident; each chunk advances the resident jobs with
-    the least remaining work (padded cells x program operations left) while
+    the least remaining work (padded cells x time steps left) while
     their cells stay within fill_cells, so a long job yields the GPU to short
     ones that arrive during it and resumes afterwards.
     policy "srpt_oldest": as srpt, and the job that arrived first among the
@@ -142,13 +143,17 @@ class Server:
     limit), which bounds how long any job can be paused.
     policy "fifo": requests are admitted in arrival order while their cells
     fit fill_cells, and every admitted job advances each chunk.
+    grad_ckpt: the checkpoint policy of gradient requests that name none, a
+    spec as for api.gradient ("all", "every:K", "revolve:SLOTS|BUDGET";
+    None: every chunk steps); a revolve job keeps SLOTS snapshots in place
+    of nt/K and recomputes more.
     On the full-size request stream at 0.5x to 1.0x the saturated rate, srpt
     cuts the median latency 3x to 12x against one-at-a-time serving; p99 is
     lower at 0.5x and 0.8x and about 15 % higher at full load, where the
     largest jobs yield to a steady stream of short ones."""
 
     def __init__(self, device="cuda", hbm_budget=None, max_active=64, chunk=50,
-                 keep_outputs=False, fill_cells=24_000_000, policy="srpt"):
+                 keep_outputs=False, fill_cells=24_000_000, policy="srpt", grad_ckpt=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -169,6 +174,7 @@ class Server:
         if policy not in POLICIES:
             raise ValueError("policy must be one of %s" % (POLICIES,))
         self.policy = policy
+        self.grad_ckpt = grad_ckpt
         self.ws = None
 
     # ---------------------------------------------------------------- sizes
@@ -183,11 +189,19 @@ class Server:
         p.nshots, p.nrec = 1, P.nrec
         return p
 
+    def _ckpt(self, req: Request):
+        """The checkpoint policy of a gradient request (None: every chunk)."""
+        spec = req.ckpt or self.grad_ckpt
+        if req.kind != "gradient" or spec is None:
+            return None
+        from . import api
+        return api.parse_ckpt(spec)
+
     def footprint(self, req: Request) -> int:
         from . import _lib
         P = req.problem
         kind = _lib.JOB_GRADIENT if req.kind == "gradient" else _lib.JOB_FORWARD
-        job = _lib.fwi_job_bytes(self._problem(P), kind, self.chunk)
+        job = _lib.fwi_job_bytes(self._problem(P), kind, self.chunk, self._ckpt(req))
         io = 4 * (P.v.size + P.nt + P.nt * P.nrec * (2 if req.kind == "gradient" else 1))
         io += 4 * P.v.size if req.kind == "gradient" else 0
         return job + io + 4 * P.src_pos.size + 4 * P.rec_pos.size
@@ -211,6 +225,12 @@ class Server:
             raise ValueError("request %d: wavelet must be [1][%d]" % (req.rid, nt))
         if req.kind == "gradient" and np.shape(req.obs) != (1, nt, P.nrec):
             raise ValueError("request %d: obs must be [1][%d][%d]" % (req.rid, nt, P.nrec))
+        if req.ckpt is not None:
+            from . import api
+            try:
+                api.parse_ckpt(req.ckpt)
+            except (ValueError, IndexError):
+                raise ValueError("request %d: bad checkpoint spec %r" % (req.rid, req.ckpt))
 
     def _admit(self, req: Request, now):
         from . import _lib
@@ -231,12 +251,13 @@ class Server:
         a.dv = torch.empty_like(a.v) if grad else None
         kind = _lib.JOB_GRADIENT if grad else _lib.JOB_FORWARD
         prob = self._problem(P)
-        nbytes = _lib.fwi_job_bytes(prob, kind, self.chunk)
+        ckpt = self._ckpt(req)
+        nbytes = _lib.fwi_job_bytes(prob, kind, self.chunk, ckpt)
         a.mem = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
         a.footprint = self.footprint(req)
         stream = torch.cuda.current_stream(dev).cuda_stream
         a.handle = _lib.fwi_job_create(
-            prob, kind, self.chunk, a.v.data_ptr(), a.w.data_ptr(), a.s.data_ptr(),
+            prob, kind, self.chunk, ckpt, a.v.data_ptr(), a.w.data_ptr(), a.s.data_ptr(),
             a.r.data_ptr() if P.nrec else None, a.obs.data_ptr() if grad and P.nrec else None,
             a.traces.data_ptr() if P.nrec else None, a.dv.data_ptr() if grad else None,
             a.mem.data_ptr(), a.mem.numel(), stream)
@@ -347,7 +368,7 @@ class Server:
         cells = 0
         st = torch.cuda.current_stream(self.device)
         stream = st.cuda_stream
-        ws_bytes = _lib.fwi_jobs_ws_bytes(self.max_active)
+        ws_bytes = _lib.fwi_jobs_ws_bytes(self.max_active, self.chunk)
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
         torch.cuda.synchronize(self.device)
         t0 = time.perf_counter()

@@ -95,6 +95,33 @@ def test_workspace_sizes_grow_with_the_policy():
     assert _lib.fwi_workspace_bytes(p, _lib.MODE_CKPT_BUF, ck_all) >= 301 * 4 * 4 * cells
 
 
+def test_job_sizes_follow_the_checkpoint_policy():
+    """A served gradient job is sized by its own policy: NULL means every
+    `chunk` steps, as an explicit every:chunk does; a revolve job with a few
+    slots needs less memory than one with a snapshot every chunk."""
+    p = _prob(nt=600, nshots=1)
+    every = _lib.fwi_job_bytes(p, _lib.JOB_GRADIENT, 20)
+    assert every == _lib.fwi_job_bytes(p, _lib.JOB_GRADIENT, 20,
+                                       _lib.FwiCkpt(kind=_lib.CKPT_EVERY, every=20))
+    rev = _lib.fwi_job_bytes(p, _lib.JOB_GRADIENT, 20, _lib.FwiCkpt(kind=_lib.CKPT_REVOLVE,
+                                                                    slots=4))
+    assert _lib.fwi_job_bytes(p, _lib.JOB_FORWARD, 20) < rev < every
+    with pytest.raises(_lib.FwiError) as e:
+        _lib.fwi_job_bytes(p, _lib.JOB_GRADIENT, 20, _lib.FwiCkpt(kind=7))
+    assert e.value.status == _lib.FWI_EINVAL
+
+
+def test_advance_workspace_grows_with_jobs_and_steps():
+    a = _lib.fwi_jobs_ws_bytes(8, 10)
+    assert _lib.fwi_jobs_ws_bytes(8, 50) > a and _lib.fwi_jobs_ws_bytes(16, 10) > a
+    lib = _lib.load()
+    out = ctypes.c_uint64()
+    assert lib.fwi_jobs_ws_bytes(8, 0, ctypes.byref(out)) == _lib.FWI_EINVAL
+    assert lib.fwi_jobs_ws_bytes(-1, 4, ctypes.byref(out)) == _lib.FWI_EINVAL
+    # too small a workspace is refused before any job is touched
+    assert lib.fwi_jobs_advance(None, 0, 4, None, 0, None) == _lib.FWI_ENOMEM
+
+
 # ------------------------------------------------------ revolve placement
 def _replay_plan(nt, slots):
     """Replays the library's binomial-checkpointing launches with labelled

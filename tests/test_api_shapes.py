@@ -72,8 +72,12 @@ def test_serving_requests_checked():
     serve.Server.check_request(serve.Request(0, "forward", 0.0, P))
     g = serve.Request(1, "gradient", 0.0, P, obs=np.zeros((1, 15, 4), np.float32))
     serve.Server.check_request(g)
+    serve.Server.check_request(serve.Request(5, "gradient", 0.0, P, obs=g.obs,
+                                             ckpt="revolve:3"))
     for bad in (serve.Request(2, "gradient", 0.0, P, obs=np.zeros((1, 14, 4))),
-                serve.Request(3, "other", 0.0, P)):
+                serve.Request(3, "other", 0.0, P),
+                serve.Request(6, "gradient", 0.0, P, obs=g.obs, ckpt="binomial:3"),
+                serve.Request(7, "gradient", 0.0, P, obs=g.obs, ckpt="every:")):
         with pytest.raises(ValueError):
             serve.Server.check_request(bad)
     Q = wl.small_2d(nz=20, nx=30, nt=15, nrec=4)

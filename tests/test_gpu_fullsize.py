@@ -73,7 +73,7 @@ def _autograd_c3(P, obs, v0):
     loss = ((tr.double() - dev(obs, torch.float64)) ** 2).sum()
     loss.backward()
     torch.cuda.synchronize()
-    return float(loss), vt.grad.cpu().numpy().astype(np.float64)
+    return float(loss.detach()), vt.grad.cpu().numpy().astype(np.float64)
 
 
 @pytest.mark.slow

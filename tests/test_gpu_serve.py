@@ -22,7 +22,7 @@ def _stream(n, scale, seed=21, force=None):
     return reqs
 
 
-def _standalone(req, chunk):
+def _standalone(req, chunk, ckpt=None):
     import torch
     from gpu_common import cfg, dev, inputs
     from paper_1912_08063_amd import api
@@ -33,7 +33,7 @@ def _standalone(req, chunk):
         torch.cuda.synchronize()
         return tr.cpu().numpy(), None, None
     mis, dv, tr = api.gradient(v, dev(req.obs, torch.float32), w, s, r,
-                               cfg(P, "every:%d" % chunk), return_traces=True)
+                               cfg(P, ckpt or "every:%d" % chunk), return_traces=True)
     torch.cuda.synchronize()
     return tr.cpu().numpy(), dv.cpu().numpy(), mis
 
@@ -205,3 +205,48 @@ def test_a_failing_request_is_retired_and_the_others_are_unchanged():
         assert np.array_equal(a.traces, b.traces)
         if a.kind == "gradient":
             assert np.array_equal(a.dv, b.dv) and a.misfit == b.misfit
+
+
+@pytest.mark.parametrize("chunk", [7, 16])
+def test_revolve_jobs_equal_standalone_revolve_calls(chunk):
+    """Gradient jobs with binomial checkpointing turn between recomputation
+    and adjoint steps inside a chunk (per-step level lists).  Served with
+    every-K gradients and forward jobs, 2-D and 3-D, 8th and 16th order, each
+    is bitwise the stand-alone fwi_gradient with the same revolve:S policy
+    (which keeps its snapshots in place instead of copying them)."""
+    from paper_1912_08063_amd import serve
+    probs = [("gradient", "revolve:3", wl.small_2d(nz=28, nx=75, nt=61, order=8, nrec=7, seed=4)),
+             ("gradient", "revolve:5", wl.small_3d(shape=(14, 12, 70), nt=47, order=16, nrec=6,
+                                                   seed=5)),
+             ("gradient", "revolve:1", wl.small_2d(nz=30, nx=40, nt=23, order=16, nrec=5, seed=7)),
+             ("gradient", "revolve:2", wl.small_3d(shape=(12, 15, 66), nt=39, order=8, nrec=8,
+                                                   seed=6)),
+             ("gradient", None, wl.small_2d(nz=26, nx=50, nt=44, order=8, nrec=6, seed=8)),
+             ("forward", None, wl.small_3d(shape=(13, 14, 60), nt=35, order=8, nrec=5, seed=9))]
+    reqs = [serve.Request(i, kind, 0.0, f32(P), ckpt=ck) for i, (kind, ck, P) in enumerate(probs)]
+    serve.attach_observed(reqs)
+    results, rep = serve.Server(max_active=6, chunk=chunk, keep_outputs=True,
+                                policy="fifo").run(reqs, realtime=False)
+    assert rep["requests"] == 6 and rep["failed"] == 0
+    for req, res in zip(reqs, results):
+        tr, dv, mis = _standalone(req, chunk, req.ckpt)
+        assert np.array_equal(res.traces, tr), req.problem.name
+        if req.kind == "gradient":
+            assert np.array_equal(res.dv, dv), req.problem.name
+            assert res.misfit == mis
+
+
+def test_revolve_job_alone_matches_oracle():
+    """A served revolve job alone (fill limit 1: nothing shares its launches
+    after the first chunk) against the FP64 oracle's misfit and gradient."""
+    from paper_1912_08063_amd import serve
+    P = f32(wl.small_2d(nz=36, nx=64, nt=80, order=8, nrec=9, seed=12))
+    req = serve.Request(0, "gradient", 0.0, P, ckpt="revolve:4")
+    serve.attach_observed([req])
+    (res,), rep = serve.Server(max_active=1, chunk=9, keep_outputs=True).run([req],
+                                                                             realtime=False)
+    assert rep["failed"] == 0
+    obs = req.obs.astype(np.float64)
+    mis_o, dv_o = oracle_gradient(P, P.v, obs)
+    assert rel_l2(res.dv.astype(np.float64), dv_o) <= 1e-3
+    assert abs(res.misfit - mis_o) <= 1e-3 * mis_o
