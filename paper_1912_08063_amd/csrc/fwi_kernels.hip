@@ -112,7 +112,11 @@ __device__ __forceinline__ int mod_pos(int a, int R) { int m = a % R; return m <
 // level list (kNoLevel: no step of this launch's direction in that round).
 __device__ __forceinline__ int step_level(const Job *__restrict__ J, int step, bool adj)
 {
-    if (J->lev) return J->lev[step];
+    // The list entry is block-uniform, but the compiler cannot see that through
+    // a global load; without readfirstlane every plane base and buffer
+    // resource derived from it would be built lane by lane (waterfall loops,
+    // 20 % slower steps).
+    if (J->lev) return __builtin_amdgcn_readfirstlane(J->lev[step]);
     return adj ? J->k0 - step : J->n0 + step;
 }
 
@@ -1341,9 +1345,9 @@ void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st)
 
 // The 16th-order adjoint runs as two single-field passes (imaging condition,
 // then the psi update): the fused kernel carries two 17-plane queues at 2
-// waves per SIMD, each pass one queue at 4 (300 vs 2 x ~115 us per step on a
-// 304^3 grid).  Both compute bitwise the same values.  At 8th order the fused
-// kernel is as fast as the two passes (207 vs 106 + 99 us) and stays;
+// waves per SIMD, each pass one queue at 4 (300 vs 117 + 131 us per step on
+// a 304^3 grid).  Both compute bitwise the same values.  At 8th order the
+// fused kernel is as fast as the two passes (205 vs 106 + 100 us) and stays;
 // FWI_SPLIT_ADJ=1 selects the two passes there too.
 template <int M>
 static bool split_adjoint()
@@ -1415,6 +1419,7 @@ static void launch_step_m(int ndim, int nw, bool adj, const Job *jobs, const int
         switch (nw) {   // wavefronts per block x rows per thread
         case 8: launch_3d<M, 8, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, lm, st); break;
         case 42: launch_3d<M, 4, 2>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, lm, st); break;
+        case 82: launch_3d<M, 8, 2>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, lm, st); break;
         default: launch_3d<M, 4, 4>(adj, jobs, prefix, njobs, step, ttiles, grid, remap, lm, st); break;
         }
     } else if (nw == 1) {   // one-row tiles, one cell per lane
@@ -1443,6 +1448,7 @@ static int occupancy_m(int ndim, int nw, bool adj)
     if (ndim == 3) {
         if (nw == 8) e = occupancy_3d<M, 8, 4>(&n, adj);
         else if (nw == 42) e = occupancy_3d<M, 4, 2>(&n, adj);
+        else if (nw == 82) e = occupancy_3d<M, 8, 2>(&n, adj);
         else e = occupancy_3d<M, 4, 4>(&n, adj);
     } else {
         e = adj ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_step2d<M, true>, 64, 0)

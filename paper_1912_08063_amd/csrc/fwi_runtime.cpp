@@ -294,19 +294,22 @@ void make_layout(const fwi_problem *p, const Geometry &g, const Policy &po, int 
     L->ck_total = c.off;
 }
 
-// 3-D block shape code: 4 (4 wavefronts, 4 rows per thread), 8 (8, 4) or
-// 42 (4 wavefronts, 2 rows per thread).  Forward launches default to 4; the
-// adjoint kernel, which carries two fields, to 42 (fewer registers per
-// thread, twice the resident waves).
-// The 16th-order stencil (M = 8) needs twice the queue: 2 rows per thread
-// in both directions.
+// 3-D block shape code: 4 (4 wavefronts, 4 rows per thread), 8 (8, 4),
+// 42 (4 wavefronts, 2 rows per thread) or 82 (8, 2).  8th-order forward
+// launches default to 4 (154 registers, 3 waves per SIMD; 82 measured 17 %
+// slower).  The adjoint, which carries two fields, and the 16th-order
+// stencil, which needs twice the queue, default to 82: 2 rows per thread
+// keep 4 waves per SIMD resident, and the 16-row tile halves the halo rows
+// of 42's 8-row tile (on a 304^3 grid: 16th-order forward 112 vs 115 us,
+// its two adjoint passes 248 vs 270 us, the 8th-order fused adjoint 205 vs
+// 207 us).
 int shape_code(bool adj, int M)
 {
     if (const char *e = getenv(adj ? "FWI_WAVES_ADJ" : "FWI_WAVES")) {
         const int v = atoi(e);
-        if (v == 4 || v == 8 || v == 42) return v;
+        if (v == 4 || v == 8 || v == 42 || v == 82) return v;
     }
-    return adj || M >= 8 ? 42 : 4;
+    return adj || M >= 8 ? 82 : 4;
 }
 // 2-D launches: grids too small to fill the GPU take the one-cell-per-lane
 // kernel with one-row tiles (shape code 1), whose launch is one round of load
@@ -321,8 +324,8 @@ bool direct_2d(const Geometry &g, int njobs)
     return (int64_t)njobs * g.nz * g.nx <= kDirect2dCells;
 }
 
-int block_waves(int code) { return code == 8 ? 8 : 4; }
-int block_rows(int code) { return code == 42 ? 2 : 4; }
+int block_waves(int code) { return code == 8 || code == 82 ? 8 : 4; }
+int block_rows(int code) { return code == 42 || code == 82 ? 2 : 4; }
 
 void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *nzc, int *zc)
 {
