@@ -116,6 +116,24 @@ def test_srpt_pauses_long_jobs_without_changing_results():
             assert np.array_equal(a.dv, b.dv) and a.misfit == b.misfit
 
 
+def test_every_policy_gives_the_same_results():
+    """The scheduling policy decides only which jobs advance in which chunk:
+    under a fill limit that forces pauses, every policy's results are bitwise
+    those of the FIFO server."""
+    from paper_1912_08063_amd import serve
+    reqs = _stream(7, 0.06, seed=43)
+    ref, _ = serve.Server(max_active=7, chunk=12, keep_outputs=True, policy="fifo",
+                          fill_cells=10 ** 12).run(reqs, realtime=False)
+    for policy in serve.POLICIES:
+        got, rep = serve.Server(max_active=7, chunk=12, keep_outputs=True, policy=policy,
+                                fill_cells=150_000).run(reqs, realtime=False)
+        assert rep["requests"] == 7 and rep["policy"] == policy
+        for a, b in zip(ref, got):
+            assert np.array_equal(a.traces, b.traces), policy
+            if a.kind == "gradient":
+                assert np.array_equal(a.dv, b.dv) and a.misfit == b.misfit, policy
+
+
 def test_mixed_orders_in_one_advance():
     """8th- and 16th-order jobs, 2-D and 3-D, forward and gradient, advanced
     together: each (dimension, order, phase) forms its own launch group, and
