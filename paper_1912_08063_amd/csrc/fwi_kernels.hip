@@ -1001,6 +1001,152 @@ __global__ void k_snapshot(const Job *__restrict__ jobs, int slot, int time, int
     }
 }
 
+// Several forward steps of a small 2-D grid in one launch (temporal blocking
+// for launch-bound grids).  A block loads a region of p^n, p^{n-1} and kappa'
+// into LDS that extends the output tile by A = K M cells on every side, then
+// advances it kk <= K steps in LDS, each step on a region M cells narrower
+// (the apron cells are computed redundantly by neighbouring blocks), and
+// stores levels n+kk and n+kk-1 of its output tile.  Cells outside the padded
+// grid hold zero and are never updated, as the frame in memory.  Each cell's
+// arithmetic is k_step2d_direct's, term by term, so the fields and traces are
+// bitwise those of kk single steps.  The launch reads ring slots n, n-1 and
+// writes slots n+kk, n+kk-1, which must differ (ring length >= K + 2): no
+// block reads what another writes.  Traces of levels n .. n+kk are written by
+// the block whose output tile holds the receiver (level n too: a preceding
+// single step does not sample the level it produces).
+template <int M, int K>
+struct Multi2d {
+    static constexpr int A = K * M;                     // apron
+    static constexpr int RW = 64;                        // region width (one wave per row)
+    static constexpr int OX = RW - 2 * A, OZ = 16;       // output tile
+    static constexpr int RH = OZ + 2 * A, NR = RW * RH;  // region
+    static_assert(OX >= 16, "apron too wide for the region");
+};
+
+template <int M, int K>
+__global__ __launch_bounds__(1024) void k_step2d_multi(const Job *__restrict__ jobs,
+                                                       int tiles_per_job, int ntxm, int step,
+                                                       int kk, int record)
+{
+    using G = Multi2d<M, K>;
+    constexpr int A = G::A, RW = G::RW, OX = G::OX, OZ = G::OZ, RH = G::RH, NR = G::NR;
+    constexpr int NT = 1024, CPT = (NR + NT - 1) / NT;   // region cells per thread
+    constexpr int RPT = 2;                               // receivers resolved per thread
+    constexpr Weights<M> W{};
+    constexpr int KD = kDiffRadii < M ? kDiffRadii : M;
+    __shared__ float s0[NR], s1[NR], sk[NR];
+
+    const int tid = threadIdx.x;
+    const int j = blockIdx.x / tiles_per_job, t = blockIdx.x % tiles_per_job;
+    const Job *__restrict__ J = jobs + j;
+    const int n = step_level(J, step, false);
+    const int nz = J->nz, nx = J->nx, pitch = J->pitch, nb = J->nb, nrec = J->nrec;
+    const int x0 = (t % ntxm) * OX - A, z0 = (t / ntxm) * OZ - A;   // region origin
+    const gfloat *cur = gptr(level_ptr(J, LevelMap{}, n));
+    const gfloat *prv = gptr(level_ptr(J, LevelMap{}, n - 1));
+    const gfloat *kap = gptr(J->kappa);
+    gfloat *o1 = gptr(level_ptr(J, LevelMap{}, n + kk));
+    gfloat *o0 = gptr(level_ptr(J, LevelMap{}, n + kk - 1));
+    const float eta_dt = J->eta_dt;
+    const int64_t p64 = pitch;
+
+    // this thread's region cells: LDS index, grid coordinates, inside the grid
+    int ci[CPT], cx[CPT], cz[CPT];
+    bool cin[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        ci[q] = tid + q * NT;
+        cx[q] = x0 + ci[q] % RW;
+        cz[q] = z0 + ci[q] / RW;
+        cin[q] = ci[q] < NR && cx[q] >= 0 && cx[q] < nx && cz[q] >= 0 && cz[q] < nz;
+    }
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        if (ci[q] >= NR) continue;
+        const int64_t off = (int64_t)(cz[q] + M) * p64 + (cx[q] + M);
+        s0[ci[q]] = cin[q] ? cur[off] : 0.f;
+        s1[ci[q]] = cin[q] ? prv[off] : 0.f;
+        sk[ci[q]] = cin[q] ? kap[off] : 0.f;
+    }
+    // receivers in this block's output tile: their LDS index (-1: elsewhere).
+    // Grids on this path are small, so field offsets fit 32 bits.
+    const bool rec_on = record && J->record;
+    auto local_of = [&](int r) {
+        const int off = (int)J->rec_off[r];
+        const int rx = off % pitch - M - x0, rz = off / pitch - M - z0;
+        return rx >= A && rx < A + OX && rz >= A && rz < A + OZ ? rz * RW + rx : -1;
+    };
+    int rl[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = tid + q * NT;
+        rl[q] = rec_on && r < nrec ? local_of(r) : -1;
+    }
+    // traces of level L (1 .. nt) from the LDS field f
+    auto sample = [&](const float *f, int L) {
+        if (!rec_on || L < 1 || L > J->nt) return;
+        float *tr = J->traces + (int64_t)(L - 1) * nrec;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+            if (rl[q] >= 0) tr[tid + q * NT] = f[rl[q]];
+        for (int r = tid + RPT * NT; r < nrec; r += NT) {
+            const int li = local_of(r);
+            if (li >= 0) tr[r] = f[li];
+        }
+    };
+    __syncthreads();
+    sample(s0, n);
+
+    float *cu = s0, *pr = s1;   // levels L and L-1; the step writes L+1 over L-1
+    for (int st = 0; st < kk; ++st) {
+        const int L = n + st, lo = (st + 1) * M;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int i = ci[q], rx = i % RW, rz = i / RW;
+            if (!cin[q] || rx < lo || rx >= RW - lo || rz < lo || rz >= RH - lo) continue;
+            const int x = cx[q], z = cz[q];
+            const float pc = cu[i];
+            const float kv = sk[i];
+            const float pv = pr[i];
+            float acc = 0.f;
+#pragma unroll
+            for (int m = M; m > KD; --m) {
+                const float tt = (cu[i + m] + cu[i - m]) + (cu[i + m * RW] + cu[i - m * RW]);
+                acc = fmaf(W.c[m], tt, acc);
+            }
+            if constexpr (KD < M) acc = fmaf(W.t2[KD], pc, acc);
+#pragma unroll
+            for (int m = KD; m >= 1; --m) {
+                const float d = ((cu[i + m] - pc) + (cu[i - m] - pc)) +
+                                ((cu[i + m * RW] - pc) + (cu[i - m * RW] - pc));
+                acc = fmaf(W.c[m], d, acc);
+            }
+            float val = fmaf(kv, acc, 2.f * pc);
+            if (J->src_x == x && J->src_z == z) {
+#pragma clang fp contract(off)
+                const float srcv = J->src_scale * J->wavelet[L];
+                val = val + srcv;
+            }
+            const int dxs = sponge_depth(x, nx, nb), dz = sponge_depth(z, nz, nb);
+            pr[i] = leapfrog(val, pv, dxs * dxs + dz * dz, eta_dt);
+        }
+        __syncthreads();
+        float *tmp = cu;
+        cu = pr;
+        pr = tmp;
+        sample(cu, L + 1);
+    }
+
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+        const int i = ci[q], rx = i % RW, rz = i / RW;
+        if (!cin[q] || rx < A || rx >= A + OX || rz < A || rz >= A + OZ) continue;
+        const int64_t off = (int64_t)(cz[q] + M) * p64 + (cx[q] + M);
+        o1[off] = cu[i];
+        o0[off] = pr[i];
+    }
+}
+
 // Final receiver sampling (level n = n0 + step).
 __global__ void k_gather(const Job *__restrict__ jobs, const int *__restrict__ gprefix,
                          int njobs, int step, LevelMap lm)
@@ -1508,6 +1654,33 @@ void launch_snapshot(const Job *jobs, int njobs, int64_t fstride, int slot, int 
 {
     hipLaunchKernelGGL(k_snapshot, dim3(grid_for(fstride / 4, 256, 4096), 2 * njobs), dim3(256),
                        0, st, jobs, slot, time, dir, mask, lm);
+}
+
+// Multi-step 2-D forward launches: the largest step count per launch, the
+// output tile, and the launch itself (M <= 4).
+int multi2d_steps() { return 4; }
+void multi2d_tile(int M, int *ox, int *oz)
+{
+    switch (M) {
+    case 1: *ox = Multi2d<1, 4>::OX; break;
+    case 2: *ox = Multi2d<2, 4>::OX; break;
+    default: *ox = Multi2d<4, 4>::OX; break;
+    }
+    *oz = Multi2d<4, 4>::OZ;
+}
+void launch_step2d_multi(int M, const Job *jobs, int njobs, int tiles_per_job, int ntxm,
+                         int step, int kk, bool record, hipStream_t st)
+{
+    // 1024 threads: three cells of the 64 x 48 region per thread and step, so
+    // a step is a short latency chain (256 threads: 5.3 us per step)
+    const dim3 g(njobs * tiles_per_job), b(1024);
+    const int rec = record ? 1 : 0;
+    switch (M) {
+    case 1: hipLaunchKernelGGL((k_step2d_multi<1, 4>), g, b, 0, st, jobs, tiles_per_job, ntxm, step, kk, rec); break;
+    case 2: hipLaunchKernelGGL((k_step2d_multi<2, 4>), g, b, 0, st, jobs, tiles_per_job, ntxm, step, kk, rec); break;
+    case 4: hipLaunchKernelGGL((k_step2d_multi<4, 4>), g, b, 0, st, jobs, tiles_per_job, ntxm, step, kk, rec); break;
+    default: break;
+    }
 }
 
 void launch_gather(const Job *jobs, const int *gprefix, int njobs, int gblocks, int threads,

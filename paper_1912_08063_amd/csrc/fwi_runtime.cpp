@@ -48,6 +48,10 @@ void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st);
 void launch_nonfinite_level(const Job *jobs, int njobs, int L, float *partial, hipStream_t st);
 void launch_assemble(const AssembleArgs &a, Job *table, int *prefix, int32_t *levels,
                      hipStream_t st);
+int multi2d_steps();
+void multi2d_tile(int M, int *ox, int *oz);
+void launch_step2d_multi(int M, const Job *jobs, int njobs, int tiles_per_job, int ntxm,
+                         int step, int kk, bool record, hipStream_t st);
 int scratch_address(void **ptr);
 void launch_stream_probe(const float *a, const float *b, const float *c, float *o, int64_t n,
                          int variant, hipStream_t st);
@@ -179,10 +183,15 @@ struct Policy {
     int ctop = 0;    // EVERY / ALL: base of the segment kept in the ring
 };
 
+bool multi_2d(const Geometry &g, int njobs);
+
 int make_policy(const fwi_problem *p, const Geometry &g, int mode, const fwi_ckpt *ck, Policy *po)
 {
     *po = Policy{};
-    if (mode == FWI_MODE_FORWARD) { po->R = 2; return FWI_OK; }
+    if (mode == FWI_MODE_FORWARD) {
+        po->R = multi_2d(g, p->nshots) ? multi2d_steps() + 2 : 2;
+        return FWI_OK;
+    }
     if (!ck) return fail(FWI_EINVAL, "checkpoint policy is NULL");
     if (ck->reserved != 0) return fail(FWI_EINVAL, "fwi_ckpt.reserved must be 0");
     const int nt = p->nt;
@@ -323,6 +332,16 @@ bool direct_2d(const Geometry &g, int njobs)
     if (const char *e = getenv("FWI_DIRECT2D")) return atoi(e) != 0;
     return (int64_t)njobs * g.nz * g.nx <= kDirect2dCells;
 }
+// Forward-only calls on such grids (up to 8th order) advance several steps
+// per launch (k_step2d_multi); their ring holds K + 2 levels so that a
+// launch's input slots (n, n-1) and output slots (n+kk, n+kk-1) differ.
+// FWI_MULTI2D=0 keeps one step per launch.
+bool multi_2d(const Geometry &g, int njobs)
+{
+    if (g.ndim != 2 || g.M > 4 || !direct_2d(g, njobs)) return false;
+    const char *e = getenv("FWI_MULTI2D");
+    return !e || atoi(e) != 0;
+}
 
 int block_waves(int code) { return code == 8 || code == 82 ? 8 : 4; }
 int block_rows(int code) { return code == 42 || code == 82 ? 2 : 4; }
@@ -421,6 +440,10 @@ struct Ctx {
     int ttiles = 0, atiles = 0, gblocks = 0, gthreads = 64;
     int remap = 1;
     int nw = 4, nw_adj = 42;
+    // forward-only small 2-D calls: several steps per launch over
+    // mtiles = mntx x (rows of tiles) output tiles per shot
+    bool multi = false;
+    int mtiles = 0, mntx = 0;
     std::vector<int> slot_time;
     // plan mode (host only): launches are recorded here instead of issued,
     // ten int32 per launch (see fwi_revolve_plan)
@@ -462,6 +485,14 @@ int prepare(Ctx &c, const fwi_problem *p, int mode, const fwi_ckpt *ck, void *ws
     c.nw = shape_code(false, c.g.M);
     c.nw_adj = shape_code(true, c.g.M);
     if (c.g.ndim == 2) c.nw = c.nw_adj = direct_2d(c.g, p->nshots) ? 1 : 4;
+    c.multi = mode == FWI_MODE_FORWARD && multi_2d(c.g, p->nshots) &&
+              c.po.R == multi2d_steps() + 2;
+    if (c.multi) {
+        int ox = 0, oz = 0;
+        multi2d_tile(c.g.M, &ox, &oz);
+        c.mntx = (c.g.nx + ox - 1) / ox;
+        c.mtiles = c.mntx * ((c.g.nz + oz - 1) / oz);
+    }
     return FWI_OK;
 }
 
@@ -874,6 +905,18 @@ int forward_phase(Ctx &c, bool record)
         TRY(rv_to_ring(c, h, nt - 1));
         if (!c.plan) HIP_TRY(hipGetLastError());
         return FWI_OK;
+    } else if (c.multi && !c.plan) {
+        // up to multi2d_steps() steps per launch; a last single step runs alone
+        for (int n = 0; n < nt;) {
+            const int kk = std::min(nt - n, multi2d_steps());
+            if (kk >= 2) {
+                launch_step2d_multi(c.g.M, c.d_jobs, c.p->nshots, c.mtiles, c.mntx, n, kk, record,
+                                    c.st);
+            } else {
+                fwd_step(c, n, record);
+            }
+            n += kk;
+        }
     } else {
         const int K = c.po.every;
         for (int n = 0; n < nt; ++n) {

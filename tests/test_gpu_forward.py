@@ -109,3 +109,39 @@ def test_batched_shots_equal_single_shot_runs_bitwise():
 def test_run_twice_bitwise():
     P = f32(wl.small_3d(shape=(30, 33, 90), nt=50, nrec=20))
     assert np.array_equal(gpu_forward(P), gpu_forward(P))
+
+
+def _tile_edge_problem(order, nt, nshots=1, seed=31):
+    """A 2-D problem whose receivers cover one whole row and one whole column of
+    the padded grid's model part (crossing every tile edge of the multi-step
+    launches: output tiles of 56, 48 or 32 columns and 16 rows) and whose
+    source sits on a tile corner."""
+    nb = 6
+    P = wl.small_2d(nz=45, nx=97, nt=nt, order=order, nb=nb, seed=seed, nshots=nshots, nrec=1)
+    nz, nx = P.v.shape
+    row = [(16 - nb, x) for x in range(nx)]
+    col = [(z, 32 - nb) for z in range(nz)]
+    rec = np.array([row + col] * nshots, dtype=np.int64)
+    src = np.array([[16 - nb, 32 - nb]] * nshots, dtype=np.int64)
+    return wl._pack(P.name + "-edges", P.v, P.dx, P.dt, nt, order, nb, P.eta_max, src, rec)
+
+
+@pytest.mark.parametrize("order", [8, 4, 2])
+def test_2d_multi_step_launches_bitwise_equal_single_steps(order, monkeypatch):
+    """Small forward-only 2-D calls advance up to 4 steps per launch in LDS
+    (FWI_MULTI2D=0 keeps one step per launch): traces bitwise equal for step
+    counts that leave every remainder (1 .. 14 steps, a single last step
+    included), for receivers on every tile edge and a source on a tile corner,
+    and for several shots in one call."""
+    for nt, nshots in [(1, 1), (2, 1), (3, 1), (4, 2), (5, 1), (6, 1), (7, 3), (14, 1)]:
+        P = f32(_tile_edge_problem(order, nt, nshots))
+        monkeypatch.setenv("FWI_MULTI2D", "0")
+        ref = gpu_forward(P)
+        monkeypatch.setenv("FWI_MULTI2D", "1")
+        got = gpu_forward(P)
+        assert np.array_equal(got, ref), (order, nt, nshots)
+
+
+def test_2d_multi_step_launches_match_the_oracle():
+    P = _tile_edge_problem(8, 61)
+    _check(P)
