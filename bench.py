@@ -206,6 +206,36 @@ def forward16_section(dev, nt):
                               / HBM_PEAK_GBS, 4)}
 
 
+def slab_section(dev, nt, reps=3):
+    """The forward step on one GPU's share of a domain-decomposed model: a
+    128 x 1024 x 1024 slab of a 1024^3 model split along z over 8 GPUs, at its
+    real shape (halo exchange not included; the zero frame stands in for the
+    received ghost planes).  Median of `reps` runs."""
+    import numpy as np
+    import torch
+
+    from paper_1912_08063_amd import api, workloads as wl
+    P = wl.slab_3d(nt=nt)
+    t = lambda a, d: torch.as_tensor(np.ascontiguousarray(a), device=dev).to(d)
+    v, w = t(P.v, torch.float32), t(P.wavelet, torch.float32)
+    s, r = t(P.src_pos, torch.int32), t(P.rec_pos, torch.int32)
+    cfg = api.Config(dt=P.dt, dx=P.dx, order=P.order, nsponge=P.nb, eta_max=P.eta_max)
+    ws = api.Workspace()
+    tr = api.forward(v, w, s, r, cfg, workspace=ws)                 # warm-up
+    secs = median_time(lambda: api.forward(v, w, s, r, cfg, workspace=ws, out=tr), reps,
+                       torch.cuda.synchronize)
+    log("slab forward: %d steps in %.1f ms (median of %d)" % (nt, secs * 1e3, reps))
+    us = secs * 1e6 / nt
+    return {"workload": "3-D acoustic forward on one of 8 z-slabs of a 1024^3 layered model "
+                        "(128 x 1024 x 1024 cells, no sponge), 8th order, %d steps, "
+                        "256x256 receivers" % nt,
+            "Gcell_updates_per_s": round(P.padded_cells * nt / secs / 1e9, 3),
+            "us_per_step": round(us, 2),
+            "hbm_frac": round(BYTES_PER_UPDATE * P.padded_cells / (us * 1e-6) / 1e9
+                              / HBM_PEAK_GBS, 4),
+            "runs": reps}
+
+
 def cpu_gradient_2d(nt):
     """The oracle's misfit + gradient for one shot of the 2-D gradient workload,
     full length, beside the GPU's batched shots/s."""
@@ -485,12 +515,14 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sections",
-                    default="forward,ceiling,c1,forward16,gradient,gradient3d,salt3d,serve",
+                    default="forward,ceiling,c1,forward16,slab,gradient,gradient3d,salt3d,serve",
                     help="comma list of: forward (headline), ceiling (3-read/1-write stream "
-                         "probe), c1 (2-D one-shot latency), forward16 (16th order), gradient "
-                         "(2-D, 32 shots), gradient3d (headline geometry), salt3d (salt "
-                         "model, revolve), serve (request streams)")
+                         "probe), c1 (2-D one-shot latency), forward16 (16th order), slab (one "
+                         "GPU's z-slab of a 1024^3 model), gradient (2-D, 32 shots), "
+                         "gradient3d (headline geometry), salt3d (salt model, revolve), serve "
+                         "(request streams)")
     ap.add_argument("--salt-nt", type=int, default=3000)
+    ap.add_argument("--slab-nt", type=int, default=200)
     ap.add_argument("--grad-nt", type=int, default=3000)
     ap.add_argument("--grad-shots", type=int, default=32)
     ap.add_argument("--grad3d-nt", type=int, default=600)
@@ -614,6 +646,8 @@ def main():
                                            plain=not args.no_grad_plain)
     if "forward16" in sections:
         out["forward16"] = forward16_section(dev, args.fwd16_nt)
+    if "slab" in sections:
+        out["slab"] = slab_section(dev, args.slab_nt)
     if "gradient3d" in sections:
         out["gradient3d"] = gradient3d_section(dev, args.grad3d_nt, 50, args.grad3d_order)
     if "salt3d" in sections:

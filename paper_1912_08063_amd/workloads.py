@@ -180,6 +180,20 @@ def layered_3d(nt=2000, order=8, n=256, seed=2):
                  [[4, n // 2, n // 2]], rec)
 
 
+def slab_3d(nt=200, order=8, seed=6, shape=(128, 1024, 1024)):
+    """One GPU's share of a 1024^3 layered model split into 8 slabs along z
+    (128 x 1024 x 1024 cells).  No sponge: the zero frame stands in for the
+    ghost planes a neighbouring slab would send.  Receivers every 4th cell at
+    z = 4, source at the top centre."""
+    rng = np.random.default_rng(seed)
+    v = layered(shape, rng)
+    dt = dt_from_cfl(float(v.max()), 10.0, 0.4)
+    nz, ny, nx = shape
+    rec = surface_receivers(shape, 4, stride=4)
+    return _pack("slab-3d-%dx%dx%d-nt%d" % (nz, ny, nx, nt), v, 10.0, dt, nt, order, 0, 10.0,
+                 [[4, ny // 2, nx // 2]], rec)
+
+
 def shots_2d(nt=3000, order=8, nshots=32, seed=3, nz=320, nx=1024):
     rng = np.random.default_rng(seed)
     truth = smooth_random_2d(nz, nx, rng)

@@ -123,7 +123,8 @@ def _tile_edge_problem(order, nt, nshots=1, seed=31):
     col = [(z, 32 - nb) for z in range(nz)]
     rec = np.array([row + col] * nshots, dtype=np.int64)
     src = np.array([[16 - nb, 32 - nb]] * nshots, dtype=np.int64)
-    return wl._pack(P.name + "-edges", P.v, P.dx, P.dt, nt, order, nb, P.eta_max, src, rec)
+    return wl._pack(P.name + "-edges", P.v, P.dx, P.dt, nt, order, nb, 25.0, src, rec,
+                    eta_max=P.eta_max)
 
 
 @pytest.mark.parametrize("order", [8, 4, 2])
