@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -142,7 +143,7 @@ int make_geometry(const fwi_problem *p, Geometry *g)
 }
 
 // largest symbol of one axis of the central stencil, S = max_k -(c0 + 2 sum c_m cos(mk))
-double max_symbol(int order)
+double max_symbol_scan(int order)
 {
     const int M = order / 2;
     double fM = 1;
@@ -164,6 +165,22 @@ double max_symbol(int order)
         best = std::max(best, -s);
     }
     return best;
+}
+
+// The scan above costs about 0.5 ms (80 000 cosines at 8th order); every call
+// validates its time step with it, so each order's value is kept after its
+// first use (concurrent first uses compute the same value).
+double max_symbol(int order)
+{
+    static std::atomic<double> known[9];
+    const int M = order / 2;
+    if (M < 1 || M > 8) return max_symbol_scan(order);
+    double v = known[M].load(std::memory_order_relaxed);
+    if (v <= 0.0) {
+        v = max_symbol_scan(order);
+        known[M].store(v, std::memory_order_relaxed);
+    }
+    return v;
 }
 
 // Default peak damping of the sponge: a quadratic profile of width nb whose
