@@ -278,10 +278,16 @@ def cpu_gradient_3d(nt_sample, nt):
                       % (nt_sample // 2, nt_sample, secs[0], secs[1], nt)}
 
 
+def _lib_workspace_bytes(prob, spec):
+    from paper_1912_08063_amd import _lib, api
+    return _lib.fwi_workspace_bytes(prob, _lib.MODE_GRADIENT, api.parse_ckpt(spec))
+
+
 def gradient_section(dev, nt, shots, every, plain=True, reps=5):
     """2-D FWI gradient, 1024x320 model, 32 shots (median of `reps` runs each).
     Batched: one fwi_gradient call for all shots (each launch covers every
-    shot's tiles).  Autograd: the same shots through FWIForward (forward with
+    shot's tiles); also with every forward level kept instead of every-50
+    checkpoints, where the workspace fits.  Autograd: the same shots through FWIForward (forward with
     checkpoints, then backward of the least-squares loss).  Plain: one
     fwi_gradient call per shot."""
     import numpy as np
@@ -316,6 +322,25 @@ def gradient_section(dev, nt, shots, every, plain=True, reps=5):
            "batched_shots_per_s": round(shots / tb, 3),
            "autograd_shots_per_s": round(shots / ta, 3),
            "misfit": out_mis[-1], "runs": reps}
+    # the same batched call keeping every forward level in HBM (no recompute):
+    # 3001 levels of 32 shots take 147 GB, which one MI355X holds
+    import dataclasses
+    cfg_all = dataclasses.replace(cfg, ckpt="all")
+    prob = api.make_problem(v0, nt, cfg_all, shots, P.nrec)
+    need = _lib_workspace_bytes(prob, "all")
+    free, _ = torch.cuda.mem_get_info(dev)
+    if need < 0.9 * free:
+        ws_all = api.Workspace()
+        mis_all = []
+        api.gradient(v0, obs, w, s, r, cfg_all, workspace=ws_all)   # warm-up
+        tl = median_time(lambda: mis_all.append(api.gradient(v0, obs, w, s, r, cfg_all,
+                                                             workspace=ws_all)[0]), 3, sync)
+        log("gradient batched, all levels kept: %d shots in %.3f s" % (shots, tl))
+        out.update(all_levels_shots_per_s=round(shots / tl, 3),
+                   all_levels_workspace_GB=round(need / 1e9, 1),
+                   all_levels_misfit_equal=bool(mis_all[-1] == out_mis[-1]))
+        del ws_all
+        torch.cuda.empty_cache()
     if not plain:
         return out
     ws1 = api.Workspace()
