@@ -39,7 +39,53 @@ class Config:
     order: int = 8
     nsponge: int = 20
     eta_max: Optional[float] = None   # None: the library's 3 vmax ln(1000) / (2 nsponge dx)
-    ckpt: str = "every:50"            # "all", "every:K", "revolve:SLOTS", "revolve:BUDGETe9B"
+    # "all", "every:K", "revolve:SLOTS", "revolve:BUDGETe9B", or "auto" /
+    # "auto:BUDGETe9B": the fastest of those that fits the device memory
+    # (default budget: 90 % of the free memory) -- see choose_ckpt
+    ckpt: str = "every:50"
+
+
+def choose_ckpt(prob: "_lib.FwiProblem", budget_bytes: float, mode: str = "gradient") -> str:
+    """The fastest checkpoint policy whose device memory fits budget_bytes, for
+    a gradient (mode "gradient": its workspace) or a differentiable forward
+    (mode "autograd": workspace plus checkpoint buffer).
+
+    Keeping every level ("all") recomputes nothing.  Every-K snapshots
+    recompute about one forward step per time step whatever K is, so the K
+    that needs least memory is taken (near sqrt(2 nt): K + 1 ring levels
+    plus 2 nt / K snapshot levels).  Binomial checkpointing within the budget
+    recomputes more and comes last."""
+    def need(spec):
+        ck = parse_ckpt(spec)
+        if mode == "autograd":
+            return (_lib.fwi_workspace_bytes(prob, _lib.MODE_FORWARD_CKPT, ck) +
+                    _lib.fwi_workspace_bytes(prob, _lib.MODE_CKPT_BUF, ck))
+        return _lib.fwi_workspace_bytes(prob, _lib.MODE_GRADIENT, ck)
+
+    if need("all") <= budget_bytes:
+        return "all"
+    nt = int(prob.nt)
+    k0 = max(1, int(round(math.sqrt(2 * nt))))
+    every = min(("every:%d" % k for k in range(max(1, k0 // 2), min(nt, 2 * k0) + 1)), key=need)
+    if need(every) <= budget_bytes:
+        return every
+    # snapshot budget of the binomial schedule: what is left beside one slot's
+    # fixed part
+    slot = need("revolve:2") - need("revolve:1")
+    base = need("revolve:1") - slot
+    return "revolve:%.6e" % max(0.0, float(budget_bytes) - base)
+
+
+def resolve_ckpt(spec: str, prob: "_lib.FwiProblem", device, mode: str = "gradient") -> str:
+    """A checkpoint spec with "auto" resolved for this problem (see choose_ckpt)."""
+    if not spec.startswith("auto"):
+        return spec
+    if ":" in spec:
+        budget = float(spec.split(":", 1)[1])
+    else:
+        free, _ = torch.cuda.mem_get_info(device)
+        budget = 0.9 * free
+    return choose_ckpt(prob, budget, mode)
 
 
 def parse_ckpt(spec: str) -> _lib.FwiCkpt:
@@ -182,7 +228,7 @@ def gradient(v, obs, src, src_pos, rec_pos, cfg: Config, return_traces=False,
     S, R, nt = src_pos.shape[0], rec_pos.shape[1], src.shape[1]
     _check_traces(obs, "obs", S, nt, R, v.device)
     prob = make_problem(v, nt, cfg, S, R)
-    ck = parse_ckpt(cfg.ckpt)
+    ck = parse_ckpt(resolve_ckpt(cfg.ckpt, prob, v.device))
     nbytes = _lib.fwi_workspace_bytes(prob, _lib.MODE_GRADIENT, ck)
     ws = (workspace or Workspace()).get(nbytes, v.device)
     dv = torch.empty_like(v)

@@ -17,7 +17,7 @@ from __future__ import annotations
 import torch
 
 from . import _lib
-from .api import Config, _require, _shots, make_problem, parse_ckpt
+from .api import Config, _require, _shots, make_problem, parse_ckpt, resolve_ckpt
 
 
 class FWIForward(torch.autograd.Function):
@@ -30,7 +30,7 @@ class FWIForward(torch.autograd.Function):
         src, src_pos, rec_pos = _shots(v, src, src_pos, rec_pos)
         S, R, nt = src_pos.shape[0], rec_pos.shape[1], src.shape[1]
         prob = make_problem(v, nt, cfg, S, R)
-        ck = parse_ckpt(cfg.ckpt)
+        ck = parse_ckpt(resolve_ckpt(cfg.ckpt, prob, v.device, "autograd"))
         stream = torch.cuda.current_stream(v.device).cuda_stream
         ck_bytes = _lib.fwi_workspace_bytes(prob, _lib.MODE_CKPT_BUF, ck)
         ws_bytes = _lib.fwi_workspace_bytes(prob, _lib.MODE_FORWARD_CKPT, ck)

@@ -84,3 +84,36 @@ def test_serving_requests_checked():
     Q.wavelet = Q.wavelet[:, :10]
     with pytest.raises(ValueError):
         serve.Server.check_request(serve.Request(4, "forward", 0.0, Q))
+
+
+def test_automatic_checkpoint_policy_fits_its_budget():
+    """ckpt="auto:BUDGET" takes every level when they fit, else every-K with the
+    K that needs least memory, else binomial checkpointing within the budget;
+    each choice's workspace fits the budget."""
+    import torch
+
+    from paper_1912_08063_amd import _lib, api
+    v = torch.zeros((120, 300))
+    cfg = api.Config(dt=1e-3, dx=10.0, order=8, nsponge=20)
+    prob = api.make_problem(v, 800, cfg, 4, 50)
+    need = lambda spec: _lib.fwi_workspace_bytes(prob, _lib.MODE_GRADIENT, api.parse_ckpt(spec))
+    n_all = need("all")
+    assert api.choose_ckpt(prob, n_all) == "all"
+    assert api.resolve_ckpt("auto:%d" % (n_all + 1), prob, None) == "all"
+    mid = api.choose_ckpt(prob, n_all - 1)
+    assert mid.startswith("every:")
+    k = int(mid.split(":")[1])
+    assert abs(k - 40) <= 20          # near sqrt(2 nt) = 40
+    assert need(mid) <= n_all - 1
+    assert all(need(mid) <= need("every:%d" % j) for j in (5, 20, 80, 200))
+    small = need(mid) - 1
+    rev = api.choose_ckpt(prob, small)
+    assert rev.startswith("revolve:") and need(rev) <= small
+    assert api.parse_ckpt(rev).budget_bytes > 0
+    assert api.resolve_ckpt("every:50", prob, None) == "every:50"
+    # the differentiable forward counts its workspace and its checkpoint buffer
+    ck = api.parse_ckpt("all")
+    ag_all = (_lib.fwi_workspace_bytes(prob, _lib.MODE_FORWARD_CKPT, ck) +
+              _lib.fwi_workspace_bytes(prob, _lib.MODE_CKPT_BUF, ck))
+    assert api.choose_ckpt(prob, ag_all, mode="autograd") == "all"
+    assert api.choose_ckpt(prob, ag_all - 1, mode="autograd").startswith("every:")

@@ -262,3 +262,28 @@ def test_2d_direct_and_marching_kernels_bitwise_equal(order, monkeypatch):
         out[d] = gpu_gradient(P, v0, obs, "every:13")
     (m0, g0, t0), (m1, g1, t1) = out["0"], out["1"]
     assert np.array_equal(t0, t1) and np.array_equal(g0, g1) and m0 == m1
+
+
+def test_automatic_checkpoint_policy_bitwise_equal():
+    """ckpt="auto" (every level kept here) and "auto:BUDGET" with a budget that
+    forces binomial checkpointing give the gradient of every-K bit for bit,
+    through fwi_gradient and through the autograd Function."""
+    import torch
+
+    from paper_1912_08063_amd import _lib, api
+    from paper_1912_08063_amd.autograd import FWIForward
+    P, obs, v0 = _setup(wl.small_2d(nz=30, nx=80, nt=70, nrec=9, seed=17))
+    ref = gpu_gradient(P, v0, obs, "every:8")
+    assert gpu_gradient(P, v0, obs, "auto")[0] == ref[0]
+    vt, w, s, r = inputs(P, v0)
+    prob = api.make_problem(vt, P.nt, cfg(P), 1, P.nrec)
+    small = _lib.fwi_workspace_bytes(prob, _lib.MODE_GRADIENT, api.parse_ckpt("revolve:3"))
+    assert api.resolve_ckpt("auto:%d" % small, prob, vt.device).startswith("revolve:")
+    for spec in ("auto", "auto:%d" % small):
+        mis, dv, tr = gpu_gradient(P, v0, obs, spec)
+        assert mis == ref[0] and np.array_equal(dv, ref[1]) and np.array_equal(tr, ref[2]), spec
+    vt.requires_grad_(True)
+    tr = FWIForward.apply(vt, w, s, r, cfg(P, "auto"))
+    ((tr - dev(obs, torch.float32)) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    assert rel_l2(vt.grad.cpu().numpy().astype(np.float64), ref[1]) <= 1e-6
