@@ -225,6 +225,39 @@ __device__ __forceinline__ gfloat *plane_ptr(gfloat *f, int zmem, int64_t plane)
     return f + (int64_t)zmem * plane;
 }
 
+// Compile-time loop: f(Int<I>{}) for I = B .. E-1, fully unrolled, so an
+// index derived from I can select a register.
+template <int V>
+struct Int {
+    static constexpr int value = V;
+};
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(Int<B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Byte offset past every plane: a buffer store to it is dropped by the
+// hardware's range check, so masked lanes need no branch around a store.
+constexpr uint32_t kDropOffset = 0x7ffffff0u;
+
+// Block barrier for LDS traffic only.  __syncthreads() is a workgroup fence
+// over all memory, so each wave first waits for every global load it has in
+// flight; a step kernel's prefetches for the next plane would then have to
+// arrive within the current plane.  The step kernels share nothing through
+// global memory within a launch (a cell's previous level, output and
+// gradient are read and written by the thread that owns it), so ordering
+// the LDS staging is enough.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // --------------------------------------------------------------- 3-D step
 // One block: NW wavefronts of RY rows each, a 64 (x) x NW*RY (y) tile,
 // marching a chunk of z.  Per plane z: the LDS buffer (z & 1) holds plane z of the propagated field
@@ -344,6 +377,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     const int last_row = ny + 2 * M - 1;   // memory rows per plane - 1
     bool act[RY];
     uint32_t roff[RY];   // byte offsets within a plane
+    uint32_t soff[RY];   // store offsets: kDropOffset for cells outside the grid
     int dxy2[RY];
     const int dxs = sponge_depth(x, nx, nb);
 #pragma unroll
@@ -351,6 +385,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         const int yy = ty * TY + wv * RY + i;
         act[i] = ax && yy < ny;
         roff[i] = 4u * (uint32_t)(min(yy + M, last_row) * pitch + col);
+        soff[i] = act[i] ? roff[i] : kDropOffset;
         const int d = sponge_depth(yy, ny, nb);
         dxy2[i] = d * d + dxs * dxs;
     }
@@ -386,13 +421,22 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
         if (r >= 0 && r < RY) { src_row = r; srcv = J->src_scale * J->wavelet[n]; }
     }
 
-    // ---- prologue: queue slot s (0..2M) holds plane zs + dir (s - M); plane
-    // zs in LDS.  Memory plane index = grid plane + M (the frame).
-    float q[RY][Q];
-    float f[FUSED ? RY : 1][FUSED ? Q : 1];
-    float hy[HQ ? NYH : 1][HQ ? Q : 1], hx[HQ ? NXH : 1][HQ ? Q : 1];
+    // ---- register queues.  Chunk plane j (j = -M .. npl-1+M, memory plane
+    // zs + dir j + M) lives in queue slot (j + M) % U, with U = Q + 1 slots:
+    // while plane ii is computed from slots ii .. ii+2M (mod U), the front
+    // plane ii+M+1 is loaded straight into the one free slot, so no register
+    // is copied after a load and the wave never waits for this plane's
+    // prefetches before it moves on.  kappa', the previous level (and g)
+    // alternate between two slots, plane ii in slot ii % 2.  The plane loop
+    // is unrolled by U (even), so every slot index is a compile-time constant.
+    // Halos staged from memory at the end of a plane (no halo ring) are
+    // loaded first, so that the wait for them leaves the rest in flight.
+    constexpr int U = Q + 1;
+    float q[RY][U];
+    float f[FUSED ? RY : 1][FUSED ? U : 1];
+    float hy[HQ ? NYH : 1][HQ ? U : 1], hx[HQ ? NXH : 1][HQ ? U : 1];
     if constexpr (HQ) {
-        // halo ring: slot s holds the halos of plane zs + dir (s - M) (s = M+1 .. 2M now)
+        // halos of chunk planes 1 .. M (slots M+1 .. 2M)
 #pragma unroll
         for (int s = M + 1; s < Q; ++s) {
             const rsrc_t ph = plane_rsrc(cur, zs + dir * (s - M) + M, plane, pbytes);
@@ -413,15 +457,16 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             if constexpr (FUSED) f[i][s] = ldb(pf, roff[i]);
         }
     }
-    float kv[RY], pv[RY], gv[FUSED ? RY : 1];
+    float kv[2][RY], pv[2][RY], gv[FUSED ? 2 : 1][FUSED ? RY : 1];
     {
         const rsrc_t pk = plane_rsrc(kap, zs + M, plane, pbytes);
         const rsrc_t pp = plane_rsrc(prv, zs + M, plane, pbytes);
 #pragma unroll
         for (int i = 0; i < RY; ++i) {
-            kv[i] = ldb(pk, roff[i]);
-            pv[i] = ldb(pp, roff[i]);
-            if constexpr (FUSED) gv[i] = accum ? ldb(plane_rsrc(grad, zs + M, plane, pbytes), roff[i]) : 0.f;
+            kv[0][i] = ldb(pk, roff[i]);
+            pv[0][i] = ldb(pp, roff[i]);
+            if constexpr (FUSED)
+                gv[0][i] = accum ? ldb(plane_rsrc(grad, zs + M, plane, pbytes), roff[i]) : 0.f;
         }
         const rsrc_t pc = plane_rsrc(cur, zs + M, plane, pbytes);
         const rsrc_t pf = plane_rsrc(fwd, zs + M, plane, pbytes);
@@ -445,52 +490,66 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                 if constexpr (FUSED) LF[hxl[h]] = ldb(pf, hxo[h]);
             }
     }
-    __syncthreads();
+    lds_barrier();
 
-    for (int ib = 0; ib < npl; ib += Q) {
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const int ii = ib + k;
-            if (ii < npl) {
+    // Plane ii of the chunk; k = ii % U selects the slots.  The main loop
+    // runs whole groups of U planes that all have a next plane (more), with
+    // no branch around a load or store, so the compiler's wait counts stay
+    // exact and only LDS waits remain at the barrier; the last group runs
+    // with those checks.
+    auto step_plane = [&](auto K, const int ii, const bool more) __attribute__((always_inline)) {
+            constexpr int k = decltype(K)::value;
             const int z = zs + dir * ii;   // grid plane computed now
-            const bool more = ii + 1 < npl;
-            // ---- prefetch the next plane z+dir (queue front z+dir(1+M), kappa',
-            // previous level, halos); memory plane = grid plane + M
-            float nq[RY], nk[RY], np[RY], nhy[NYH], nhx[NXH];
-            float nfq[FUSED ? RY : 1], ng[FUSED ? RY : 1], nfy[FUSED ? NYH : 1], nfx[FUSED ? NXH : 1];
+            const int c = k & 1, cn = c ^ 1;   // pointwise slots of planes ii, ii+1
+            const int fs = (k + U - 1) % U;    // free queue slot: chunk plane ii+M+1
+            // ---- prefetch: halos of plane z+dir staged at the end of this
+            // plane (without a halo ring), then the queue front z+dir(1+M)
+            // and the pointwise streams of plane z+dir; memory plane = grid
+            // plane + M
+            float nhy[HQ ? 1 : NYH], nhx[HQ ? 1 : NXH];
+            float nfy[FUSED ? NYH : 1], nfx[FUSED ? NXH : 1];
             const int zf = z + dir * (1 + M) + M, zn = z + dir + M;
             if (more) {
-                const rsrc_t pq = plane_rsrc(cur, zf, plane, pbytes);
-                const rsrc_t pk = plane_rsrc(kap, zn, plane, pbytes);
-                const rsrc_t pp = plane_rsrc(prv, zn, plane, pbytes);
-                const rsrc_t ph = plane_rsrc(cur, zn, plane, pbytes);
+                if constexpr (!HQ) {
+                    const rsrc_t ph = plane_rsrc(cur, zn, plane, pbytes);
 #pragma unroll
-                for (int i = 0; i < RY; ++i) {
-                    nq[i] = ldb(pq, roff[i]);
-                    nk[i] = ldb_stream(pk, roff[i]);
-                    np[i] = ldb_stream(pp, roff[i]);
+                    for (int h = 0; h < NYH; ++h) nhy[h] = ldb(ph, hyo[h]);
+#pragma unroll
+                    for (int h = 0; h < NXH; ++h) nhx[h] = ldb(ph, hxo[h]);
                 }
-                const rsrc_t phq = HQ ? pq : ph;
-#pragma unroll
-                for (int h = 0; h < NYH; ++h) nhy[h] = ldb(phq, hyo[h]);
-#pragma unroll
-                for (int h = 0; h < NXH; ++h) nhx[h] = ldb(phq, hxo[h]);
                 if constexpr (FUSED) {
-                    const rsrc_t fq = plane_rsrc(fwd, zf, plane, pbytes);
                     const rsrc_t fh = plane_rsrc(fwd, zn, plane, pbytes);
-                    const rsrc_t pg = plane_rsrc(grad, zn, plane, pbytes);
-#pragma unroll
-                    for (int i = 0; i < RY; ++i) {
-                        nfq[i] = ldb(fq, roff[i]);
-                        ng[i] = accum ? ldb_stream(pg, roff[i]) : 0.f;
-                    }
 #pragma unroll
                     for (int h = 0; h < NYH; ++h) nfy[h] = ldb(fh, hyo[h]);
 #pragma unroll
                     for (int h = 0; h < NXH; ++h) nfx[h] = ldb(fh, hxo[h]);
                 }
+                const rsrc_t pq = plane_rsrc(cur, zf, plane, pbytes);
+                const rsrc_t pk = plane_rsrc(kap, zn, plane, pbytes);
+                const rsrc_t pp = plane_rsrc(prv, zn, plane, pbytes);
+#pragma unroll
+                for (int i = 0; i < RY; ++i) {
+                    q[i][fs] = ldb(pq, roff[i]);
+                    kv[cn][i] = ldb_stream(pk, roff[i]);
+                    pv[cn][i] = ldb_stream(pp, roff[i]);
+                }
+                if constexpr (HQ) {
+#pragma unroll
+                    for (int h = 0; h < NYH; ++h) hy[h][fs] = ldb(pq, hyo[h]);
+#pragma unroll
+                    for (int h = 0; h < NXH; ++h) hx[h][fs] = ldb(pq, hxo[h]);
+                }
+                if constexpr (FUSED) {
+                    const rsrc_t fq = plane_rsrc(fwd, zf, plane, pbytes);
+                    const rsrc_t pg = plane_rsrc(grad, zn, plane, pbytes);
+#pragma unroll
+                    for (int i = 0; i < RY; ++i) {
+                        f[i][fs] = ldb(fq, roff[i]);
+                        gv[cn][i] = accum ? ldb_stream(pg, roff[i]) : 0.f;
+                    }
+                }
             }
-            // ---- plane z (queue slot (k + M + m) % Q holds plane z + dir m)
+            // ---- plane z (queue slot (k + M + m) % U holds plane z + dir m)
             const float *L = sp + (ii & 1) * LS;
             const float *LF = FUSED ? sf + (ii & 1) * LS : nullptr;
             const rsrc_t po = plane_rsrc(out, z + M, plane, pbytes);
@@ -500,13 +559,13 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
 #pragma unroll
             for (int i = 0; i < RY; ++i) {
                 const int ly = M + wv * RY + i, lx = M + lane;
-                const float pc = q[i][(k + M) % Q];
+                const float pc = q[i][(k + M) % U];
                 float acc = 0.f;
 #pragma unroll
                 for (int m = M; m > KD; --m) {
                     const float t = (L[ly * LX + lx + m] + L[ly * LX + lx - m]) +
                                     (L[(ly + m) * LX + lx] + L[(ly - m) * LX + lx]) +
-                                    (q[i][(k + M + m) % Q] + q[i][(k + M - m) % Q]);
+                                    (q[i][(k + M + m) % U] + q[i][(k + M - m) % U]);
                     acc = fmaf(W.c[m], t, acc);
                 }
                 if constexpr (KD < M) acc = fmaf(W.t3[KD], pc, acc);
@@ -514,12 +573,12 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                 for (int m = KD; m >= 1; --m) {
                     const float d = ((L[ly * LX + lx + m] - pc) + (L[ly * LX + lx - m] - pc)) +
                                     ((L[(ly + m) * LX + lx] - pc) + (L[(ly - m) * LX + lx] - pc)) +
-                                    ((q[i][(k + M + m) % Q] - pc) + (q[i][(k + M - m) % Q] - pc));
+                                    ((q[i][(k + M + m) % U] - pc) + (q[i][(k + M - m) % U] - pc));
                     acc = fmaf(W.c[m], d, acc);
                 }
                 // imaging: g + psi^{k+1} * L'p^k (kv holds g, pv psi^{k+1}),
                 // the same operation as the fused kernel's
-                res[i] = IMG ? fmaf(pv[i], acc, kv[i]) : fmaf(kv[i], acc, 2.f * pc);
+                res[i] = IMG ? fmaf(pv[c][i], acc, kv[c][i]) : fmaf(kv[c][i], acc, 2.f * pc);
             }
             if (src_blk && z == J->src_z) {
 #pragma unroll
@@ -527,24 +586,23 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             }
 #pragma unroll
             for (int i = 0; i < RY; ++i) {
-                if constexpr (IMG) {
-                    if (act[i]) stb_stream(po, roff[i], res[i]);
-                } else {
-                    if (act[i]) stb_stream(po, roff[i], leapfrog(res[i], pv[i], dxy2[i] + dz * dz, eta_dt));
-                }
+                if constexpr (IMG)
+                    stb_stream(po, soff[i], res[i]);
+                else
+                    stb_stream(po, soff[i], leapfrog(res[i], pv[c][i], dxy2[i] + dz * dz, eta_dt));
             }
             if constexpr (FUSED) {
                 if (accum) {
 #pragma unroll
                     for (int i = 0; i < RY; ++i) {
                         const int ly = M + wv * RY + i, lx = M + lane;
-                        const float fc = f[i][(k + M) % Q];
+                        const float fc = f[i][(k + M) % U];
                         float lf = 0.f;
 #pragma unroll
                         for (int m = M; m > KD; --m) {
                             const float t = (LF[ly * LX + lx + m] + LF[ly * LX + lx - m]) +
                                             (LF[(ly + m) * LX + lx] + LF[(ly - m) * LX + lx]) +
-                                            (f[i][(k + M + m) % Q] + f[i][(k + M - m) % Q]);
+                                            (f[i][(k + M + m) % U] + f[i][(k + M - m) % U]);
                             lf = fmaf(W.c[m], t, lf);
                         }
                         if constexpr (KD < M) lf = fmaf(W.t3[KD], fc, lf);
@@ -553,56 +611,49 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                             const float d =
                                 ((LF[ly * LX + lx + m] - fc) + (LF[ly * LX + lx - m] - fc)) +
                                 ((LF[(ly + m) * LX + lx] - fc) + (LF[(ly - m) * LX + lx] - fc)) +
-                                ((f[i][(k + M + m) % Q] - fc) + (f[i][(k + M - m) % Q] - fc));
+                                ((f[i][(k + M + m) % U] - fc) + (f[i][(k + M - m) % U] - fc));
                             lf = fmaf(W.c[m], d, lf);
                         }
-                        if (act[i]) stb_stream(pg, roff[i], fmaf(q[i][(k + M) % Q], lf, gv[i]));
+                        stb_stream(pg, soff[i], fmaf(q[i][(k + M) % U], lf, gv[c][i]));
                     }
                 }
             }
-            // ---- rotate to plane z+dir and stage it in the other LDS buffer
+            // ---- stage plane z+dir in the other LDS buffer
             if (more) {
                 float *Ln = sp + ((ii + 1) & 1) * LS;
                 float *LFn = FUSED ? sf + ((ii + 1) & 1) * LS : nullptr;
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
-                    q[i][k] = nq[i];   // slot k held plane z - dir M
-                    kv[i] = nk[i];
-                    pv[i] = np[i];
-                    Ln[(M + wv * RY + i) * LX + M + lane] = q[i][(k + M + 1) % Q];
-                    if constexpr (FUSED) {
-                        f[i][k] = nfq[i];
-                        gv[i] = ng[i];
-                        LFn[(M + wv * RY + i) * LX + M + lane] = f[i][(k + M + 1) % Q];
-                    }
+                    Ln[(M + wv * RY + i) * LX + M + lane] = q[i][(k + M + 1) % U];
+                    if constexpr (FUSED)
+                        LFn[(M + wv * RY + i) * LX + M + lane] = f[i][(k + M + 1) % U];
                 }
 #pragma unroll
                 for (int h = 0; h < NYH; ++h)
                     if (hyl[h] >= 0) {
-                        if constexpr (HQ) {
-                            Ln[hyl[h]] = hy[h][(k + M + 1) % Q];
-                            hy[h][k] = nhy[h];
-                        } else {
-                            Ln[hyl[h]] = nhy[h];
-                        }
+                        if constexpr (HQ) Ln[hyl[h]] = hy[h][(k + M + 1) % U];
+                        else Ln[hyl[h]] = nhy[h];
                         if constexpr (FUSED) LFn[hyl[h]] = nfy[h];
                     }
 #pragma unroll
                 for (int h = 0; h < NXH; ++h)
                     if (hxl[h] >= 0) {
-                        if constexpr (HQ) {
-                            Ln[hxl[h]] = hx[h][(k + M + 1) % Q];
-                            hx[h][k] = nhx[h];
-                        } else {
-                            Ln[hxl[h]] = nhx[h];
-                        }
+                        if constexpr (HQ) Ln[hxl[h]] = hx[h][(k + M + 1) % U];
+                        else Ln[hxl[h]] = nhx[h];
                         if constexpr (FUSED) LFn[hxl[h]] = nfx[h];
                     }
             }
-            __syncthreads();
-            }
-        }
-    }
+            lds_barrier();
+    };
+    int ib = 0;
+    for (; ib + U < npl; ib += U)
+        static_for<0, U>([&](auto K) __attribute__((always_inline)) {
+            step_plane(K, ib + decltype(K)::value, true);
+        });
+    static_for<0, U>([&](auto K) __attribute__((always_inline)) {
+        const int ii = ib + decltype(K)::value;
+        if (ii < npl) step_plane(K, ii, ii + 1 < npl);
+    });
 }
 
 // --------------------------------------------------------------- 2-D step
@@ -1490,11 +1541,11 @@ void launch_vstats(const float *v, int64_t n, float *partial, hipStream_t st)
 }
 
 // The 16th-order adjoint runs as two single-field passes (imaging condition,
-// then the psi update): the fused kernel carries two 17-plane queues at 2
-// waves per SIMD, each pass one queue at 4 (300 vs 117 + 131 us per step on
-// a 304^3 grid).  Both compute bitwise the same values.  At 8th order the
-// fused kernel is as fast as the two passes (205 vs 106 + 100 us) and stays;
-// FWI_SPLIT_ADJ=1 selects the two passes there too.
+// then the psi update): the fused kernel carries two 17-plane queues in
+// more registers than fit 2 waves per SIMD, each pass one queue.  Both
+// compute bitwise the same values.  At 8th order the fused kernel is as
+// fast as the two passes and stays; FWI_SPLIT_ADJ=1 selects the two passes
+// there too.
 template <int M>
 static bool split_adjoint()
 {

@@ -322,20 +322,20 @@ void make_layout(const fwi_problem *p, const Geometry &g, const Policy &po, int 
 
 // 3-D block shape code: 4 (4 wavefronts, 4 rows per thread), 8 (8, 4),
 // 42 (4 wavefronts, 2 rows per thread) or 82 (8, 2).  8th-order forward
-// launches default to 4 (154 registers, 3 waves per SIMD; 82 measured 17 %
-// slower).  The adjoint, which carries two fields, and the 16th-order
-// stencil, which needs twice the queue, default to 82: 2 rows per thread
-// keep 4 waves per SIMD resident, and the 16-row tile halves the halo rows
-// of 42's 8-row tile (on a 304^3 grid: 16th-order forward 112 vs 115 us,
-// its two adjoint passes 248 vs 270 us, the 8th-order fused adjoint 205 vs
-// 207 us).
+// launches default to 4 (188 registers, 2 waves per SIMD, 85 us per step on
+// a 304^3 grid; 82: 90 us, 42: 93 us).  The adjoint, which carries two
+// fields, and the 16th-order stencil, which needs twice the queue, default
+// to 42 (3 waves per SIMD; on the same grid the 8th-order fused adjoint
+// makes the 600-step gradient 0.207 s against 0.215 s with 82, the
+// 16th-order forward takes 101 against 129 us: 8-wave blocks of 3 waves per
+// SIMD leave one block per CU).
 int shape_code(bool adj, int M)
 {
     if (const char *e = getenv(adj ? "FWI_WAVES_ADJ" : "FWI_WAVES")) {
         const int v = atoi(e);
         if (v == 4 || v == 8 || v == 42 || v == 82) return v;
     }
-    return adj || M >= 8 ? 82 : 4;
+    return adj || M >= 8 ? 42 : 4;
 }
 // 2-D launches: grids too small to fill the GPU take the one-cell-per-lane
 // kernel with one-row tiles (shape code 1), whose launch is one round of load
