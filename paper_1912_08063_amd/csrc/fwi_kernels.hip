@@ -273,6 +273,13 @@ __device__ __forceinline__ void lds_barrier()
 // alone, each with the forward step's memory pattern (see launch_3d).
 enum StepMode { kFwd = 0, kAdj = 1, kAdjPsi = 2, kImage = 3 };
 
+// Planes a step kernel loads ahead of the one it computes (queue front,
+// kappa', previous level).  Two planes ahead measured no faster on the
+// 304^3 forward: 86.7 against 85.1 us per step with 4 x 4 blocks (211
+// registers), 85.9 with 4 x 2.
+template <int M, int MODE>
+constexpr int kLookahead = 1;
+
 template <int M, int MODE, int NW, int RY>
 __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs,
                                                 const int *__restrict__ prefix, int njobs,
@@ -422,23 +429,27 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     }
 
     // ---- register queues.  Chunk plane j (j = -M .. npl-1+M, memory plane
-    // zs + dir j + M) lives in queue slot (j + M) % U, with U = Q + 1 slots:
-    // while plane ii is computed from slots ii .. ii+2M (mod U), the front
-    // plane ii+M+1 is loaded straight into the one free slot, so no register
-    // is copied after a load and the wave never waits for this plane's
-    // prefetches before it moves on.  kappa', the previous level (and g)
-    // alternate between two slots, plane ii in slot ii % 2.  The plane loop
-    // is unrolled by U (even), so every slot index is a compile-time constant.
-    // Halos staged from memory at the end of a plane (no halo ring) are
-    // loaded first, so that the wait for them leaves the rest in flight.
-    constexpr int U = Q + 1;
+    // zs + dir j + M) lives in queue slot (j + M) % U.  While plane ii is
+    // computed from slots ii .. ii+2M (mod U), planes up to ii+M+D-1 are
+    // already loaded and the front plane ii+M+D is loaded straight into a
+    // free slot (U >= Q + D), so no register is copied after a load and the
+    // wave never waits for recent prefetches before it moves on.  kappa', the
+    // previous level (and g) of plane ii are in slot ii % (D + 1), loaded D
+    // planes ahead.  The plane loop is unrolled by U, a multiple of D + 1,
+    // so every slot index is a compile-time constant.  Halos staged from
+    // memory at the end of a plane (no halo ring) are loaded one plane ahead,
+    // first, so that the wait for them leaves the rest in flight.
+    constexpr int D = kLookahead<M, MODE>;
+    constexpr int P = D + 1;
+    constexpr int U = (Q + D + P - 1) / P * P;
     float q[RY][U];
     float f[FUSED ? RY : 1][FUSED ? U : 1];
     float hy[HQ ? NYH : 1][HQ ? U : 1], hx[HQ ? NXH : 1][HQ ? U : 1];
     if constexpr (HQ) {
-        // halos of chunk planes 1 .. M (slots M+1 .. 2M)
+        // halos of chunk planes 1 .. M+D-1 (slots M+1 .. 2M+D-1)
 #pragma unroll
-        for (int s = M + 1; s < Q; ++s) {
+        for (int s = M + 1; s < Q + D - 1; ++s) {
+            if (s - M >= npl) continue;
             const rsrc_t ph = plane_rsrc(cur, zs + dir * (s - M) + M, plane, pbytes);
 #pragma unroll
             for (int h = 0; h < NYH; ++h) hy[h][s] = ldb(ph, hyo[h]);
@@ -446,8 +457,11 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             for (int h = 0; h < NXH; ++h) hx[h][s] = ldb(ph, hxo[h]);
         }
     }
+    // chunk planes -M .. M+D-1 (plane j is first read by the stencil of
+    // plane j - M, so planes past the chunk's last plane + M are skipped)
 #pragma unroll
-    for (int s = 0; s < Q; ++s) {
+    for (int s = 0; s < Q + D - 1; ++s) {
+        if (s >= Q && s - 2 * M >= npl) continue;
         const int zm = zs + dir * (s - M) + M;
         const rsrc_t pc = plane_rsrc(cur, zm, plane, pbytes);
         const rsrc_t pf = plane_rsrc(fwd, zm, plane, pbytes);
@@ -457,7 +471,22 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             if constexpr (FUSED) f[i][s] = ldb(pf, roff[i]);
         }
     }
-    float kv[2][RY], pv[2][RY], gv[FUSED ? 2 : 1][FUSED ? RY : 1];
+    float kv[P][RY], pv[P][RY], gv[FUSED ? P : 1][FUSED ? RY : 1];
+    // pointwise streams of planes 1 .. D-1
+#pragma unroll
+    for (int a = 1; a < D; ++a) {
+        if (a >= npl) continue;
+        const rsrc_t pk = plane_rsrc(kap, zs + dir * a + M, plane, pbytes);
+        const rsrc_t pp = plane_rsrc(prv, zs + dir * a + M, plane, pbytes);
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            kv[a][i] = ldb_stream(pk, roff[i]);
+            pv[a][i] = ldb_stream(pp, roff[i]);
+            if constexpr (FUSED)
+                gv[a][i] = accum ? ldb_stream(plane_rsrc(grad, zs + dir * a + M, plane, pbytes), roff[i])
+                                 : 0.f;
+        }
+    }
     {
         const rsrc_t pk = plane_rsrc(kap, zs + M, plane, pbytes);
         const rsrc_t pp = plane_rsrc(prv, zs + M, plane, pbytes);
@@ -497,18 +526,19 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
     // no branch around a load or store, so the compiler's wait counts stay
     // exact and only LDS waits remain at the barrier; the last group runs
     // with those checks.
-    auto step_plane = [&](auto K, const int ii, const bool more) __attribute__((always_inline)) {
+    auto step_plane = [&](auto K, const int ii, const bool more, const bool ahead)
+        __attribute__((always_inline)) {
             constexpr int k = decltype(K)::value;
             const int z = zs + dir * ii;   // grid plane computed now
-            const int c = k & 1, cn = c ^ 1;   // pointwise slots of planes ii, ii+1
-            const int fs = (k + U - 1) % U;    // free queue slot: chunk plane ii+M+1
+            const int c = k % P, cn = (k + D) % P;   // pointwise slots of planes ii, ii+D
+            const int fs = (k + Q - 1 + D) % U;      // free queue slot: chunk plane ii+M+D
             // ---- prefetch: halos of plane z+dir staged at the end of this
             // plane (without a halo ring), then the queue front z+dir(1+M)
             // and the pointwise streams of plane z+dir; memory plane = grid
             // plane + M
             float nhy[HQ ? 1 : NYH], nhx[HQ ? 1 : NXH];
             float nfy[FUSED ? NYH : 1], nfx[FUSED ? NXH : 1];
-            const int zf = z + dir * (1 + M) + M, zn = z + dir + M;
+            const int zf = z + dir * (D + M) + M, zn = z + dir + M, za = z + dir * D + M;
             if (more) {
                 if constexpr (!HQ) {
                     const rsrc_t ph = plane_rsrc(cur, zn, plane, pbytes);
@@ -524,9 +554,11 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
 #pragma unroll
                     for (int h = 0; h < NXH; ++h) nfx[h] = ldb(fh, hxo[h]);
                 }
+            }
+            if (ahead) {
                 const rsrc_t pq = plane_rsrc(cur, zf, plane, pbytes);
-                const rsrc_t pk = plane_rsrc(kap, zn, plane, pbytes);
-                const rsrc_t pp = plane_rsrc(prv, zn, plane, pbytes);
+                const rsrc_t pk = plane_rsrc(kap, za, plane, pbytes);
+                const rsrc_t pp = plane_rsrc(prv, za, plane, pbytes);
 #pragma unroll
                 for (int i = 0; i < RY; ++i) {
                     q[i][fs] = ldb(pq, roff[i]);
@@ -541,7 +573,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
                 }
                 if constexpr (FUSED) {
                     const rsrc_t fq = plane_rsrc(fwd, zf, plane, pbytes);
-                    const rsrc_t pg = plane_rsrc(grad, zn, plane, pbytes);
+                    const rsrc_t pg = plane_rsrc(grad, za, plane, pbytes);
 #pragma unroll
                     for (int i = 0; i < RY; ++i) {
                         f[i][fs] = ldb(fq, roff[i]);
@@ -646,13 +678,13 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(const Job *__restrict__ jobs
             lds_barrier();
     };
     int ib = 0;
-    for (; ib + U < npl; ib += U)
+    for (; ib + U - 1 + D < npl; ib += U)
         static_for<0, U>([&](auto K) __attribute__((always_inline)) {
-            step_plane(K, ib + decltype(K)::value, true);
+            step_plane(K, ib + decltype(K)::value, true, true);
         });
     static_for<0, U>([&](auto K) __attribute__((always_inline)) {
         const int ii = ib + decltype(K)::value;
-        if (ii < npl) step_plane(K, ii, ii + 1 < npl);
+        if (ii < npl) step_plane(K, ii, ii + 1 < npl, ii + D < npl);
     });
 }
 
@@ -731,21 +763,31 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
     const int hl = lane < M ? lane : lane + TX;
     const int hcol = tx * TX - M + hl;
     const bool hact = lane < 2 * M && hcol >= 0 && hcol < pitch;
+    const int hcl = min(max(hcol, 0), pitch - 1);   // a column inside the row
     const bool src_here = !ADJ && J->src_x == x && J->src_z >= z0 && J->src_z < z1;
     const float srcv = src_here ? J->src_scale * J->wavelet[n] : 0.f;
     const int64_t p64 = pitch;
 
-    float q[Q];
-    float f[ADJ ? Q : 1];
+    // Register queue of U = Q + 1 rows: chunk row j (row z0 + j, j = -M ..)
+    // in slot (j + M) % U; the front row is loaded straight into the free
+    // slot and kappa', the previous level (and g) alternate between two
+    // slots, so no freshly loaded register is copied and the wave keeps the
+    // next row's loads in flight while it computes (as in the 3-D kernel).
+    // Lanes outside the grid load and store zeros in the row's frame and
+    // padding, which hold zeros, so stores need no mask.
+    constexpr int U = Q + 1;
+    float q[U];
+    float f[ADJ ? U : 1];
 #pragma unroll
     for (int s = 0; s < Q; ++s) {   // rows z0 - M .. z0 + M
         q[s] = act ? cur[(int64_t)(z0 + s) * p64 + col] : 0.f;
         if constexpr (ADJ) f[s] = act ? fwd[(int64_t)(z0 + s) * p64 + col] : 0.f;
     }
-    float kv = act ? kap[(int64_t)(z0 + M) * p64 + col] : 0.f;
-    float pv = act ? prv[(int64_t)(z0 + M) * p64 + col] : 0.f;
-    float gv = 0.f;
-    if constexpr (ADJ) gv = act && accum ? grad[(int64_t)(z0 + M) * p64 + col] : 0.f;
+    float kv[2], pv[2], gv[2];
+    kv[0] = act ? kap[(int64_t)(z0 + M) * p64 + col] : 0.f;
+    pv[0] = act ? prv[(int64_t)(z0 + M) * p64 + col] : 0.f;
+    gv[0] = 0.f;
+    if constexpr (ADJ) gv[0] = act && accum ? grad[(int64_t)(z0 + M) * p64 + col] : 0.f;
     {
         float *L = sp + (z0 & 1) * LX;
         L[M + lane] = q[M];
@@ -756,48 +798,56 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
             if (lane < 2 * M) LF[hl] = hact ? fwd[(int64_t)(z0 + M) * p64 + hcol] : 0.f;
         }
     }
-    __syncthreads();
+    lds_barrier();
 
-    for (int zb = z0; zb < z1; zb += Q) {
-#pragma unroll
-        for (int k = 0; k < Q; ++k) {
-            const int z = zb + k;
-            if (z < z1) {
-            const bool more = z + 1 < z1;
-            float nq = 0.f, nk = 0.f, np = 0.f, nh = 0.f, nfq = 0.f, nfh = 0.f, ng = 0.f;
+    // row z = z0 + ii; k = ii % U selects the slots
+    auto step_row = [&](auto K, const int z, const bool more) __attribute__((always_inline)) {
+            constexpr int k = decltype(K)::value;
+            const int c = k & 1, cn = c ^ 1;   // pointwise slots of rows z, z+1
+            const int fs = (k + U - 1) % U;    // free queue slot: row z+M+1
+            // halos of row z+1 (staged at the end of this row) first.  The
+            // loads are not predicated (a skipped load would make the wait
+            // counts after it inexact): lanes outside the grid read the zero
+            // frame and padding of their row, halo lanes a clamped column.
+            float nh = 0.f, nfh = 0.f;
             if (more) {
                 const int64_t rf = (int64_t)(z + 1 + 2 * M) * p64, rc = (int64_t)(z + 1 + M) * p64;
-                nq = act ? cur[rf + col] : 0.f;
-                nk = act ? kap[rc + col] : 0.f;
-                np = act ? prv[rc + col] : 0.f;
-                nh = hact ? cur[rc + hcol] : 0.f;
+                const float h = cur[rc + hcl];
+                nh = hact ? h : 0.f;
                 if constexpr (ADJ) {
-                    nfq = act ? fwd[rf + col] : 0.f;
-                    nfh = hact ? fwd[rc + hcol] : 0.f;
-                    ng = act && accum ? grad[rc + col] : 0.f;
+                    const float hf = fwd[rc + hcl];
+                    nfh = hact ? hf : 0.f;
+                }
+                q[fs] = cur[rf + col];
+                kv[cn] = kap[rc + col];
+                pv[cn] = prv[rc + col];
+                if constexpr (ADJ) {
+                    f[fs] = fwd[rf + col];
+                    const float g = grad[rc + col];
+                    gv[cn] = accum ? g : 0.f;
                 }
             }
             const float *L = sp + (z & 1) * LX;
             const int lx = M + lane;
-            const float pc = q[(k + M) % Q];
+            const float pc = q[(k + M) % U];
             float acc = 0.f;
 #pragma unroll
             for (int m = M; m > KD; --m) {
-                const float t = (L[lx + m] + L[lx - m]) + (q[(k + M + m) % Q] + q[(k + M - m) % Q]);
+                const float t = (L[lx + m] + L[lx - m]) + (q[(k + M + m) % U] + q[(k + M - m) % U]);
                 acc = fmaf(W.c[m], t, acc);
             }
             if constexpr (KD < M) acc = fmaf(W.t2[KD], pc, acc);
 #pragma unroll
             for (int m = KD; m >= 1; --m) {
                 const float d = ((L[lx + m] - pc) + (L[lx - m] - pc)) +
-                                ((q[(k + M + m) % Q] - pc) + (q[(k + M - m) % Q] - pc));
+                                ((q[(k + M + m) % U] - pc) + (q[(k + M - m) % U] - pc));
                 acc = fmaf(W.c[m], d, acc);
             }
-            float val = fmaf(kv, acc, 2.f * pc);
+            float val = fmaf(kv[c], acc, 2.f * pc);
             if (src_here && z == J->src_z) val += srcv;
             const int dz = sponge_depth(z, nz, nb);
             const int64_t rz = (int64_t)(z + M) * p64 + col;
-            float o = leapfrog(val, pv, dxs * dxs + dz * dz, eta_dt);
+            float o = leapfrog(val, pv[c], dxs * dxs + dz * dz, eta_dt);
             if constexpr (ADJ) {
                 // receivers on row z: lane i takes the list's i-th, and the sum
                 // reaches the lane of its column through LDS
@@ -806,54 +856,56 @@ __global__ __launch_bounds__(64) void k_step2d(const Job *__restrict__ jobs,
                     const int key = idx < re ? J->rt_key[idx] : -1;
                     const int r = key >= 0 && (key >> 6) == z ? J->rt_rec[idx] : -1;
                     sinj[lane] = 0.f;
-                    __syncthreads();
+                    lds_barrier();
                     if (r >= 0) sinj[key & 63] = adj_source(J, n, r);
-                    __syncthreads();
-                    if (act) o += kv * sinj[lane];
+                    lds_barrier();
+                    if (act) o += kv[c] * sinj[lane];
                     rp += __popcll(__ballot(r >= 0));
-                    __syncthreads();
+                    lds_barrier();
                 }
             }
-            if (act) out[rz] = o;
+            out[rz] = o;   // zero outside the grid
             if constexpr (ADJ) {
                 if (accum) {
                     const float *LF = sf + (z & 1) * LX;
-                    const float fc = f[(k + M) % Q];
+                    const float fc = f[(k + M) % U];
                     float lf = 0.f;
 #pragma unroll
                     for (int m = M; m > KD; --m) {
-                        const float t = (LF[lx + m] + LF[lx - m]) + (f[(k + M + m) % Q] + f[(k + M - m) % Q]);
+                        const float t = (LF[lx + m] + LF[lx - m]) + (f[(k + M + m) % U] + f[(k + M - m) % U]);
                         lf = fmaf(W.c[m], t, lf);
                     }
                     if constexpr (KD < M) lf = fmaf(W.t2[KD], fc, lf);
 #pragma unroll
                     for (int m = KD; m >= 1; --m) {
                         const float d = ((LF[lx + m] - fc) + (LF[lx - m] - fc)) +
-                                        ((f[(k + M + m) % Q] - fc) + (f[(k + M - m) % Q] - fc));
+                                        ((f[(k + M + m) % U] - fc) + (f[(k + M - m) % U] - fc));
                         lf = fmaf(W.c[m], d, lf);
                     }
-                    if (act) grad[rz] = fmaf(pc, lf, gv);
+                    grad[rz] = fmaf(pc, lf, gv[c]);   // zero outside the grid
                 }
             }
             if (more) {
-                q[k] = nq;
-                kv = nk;
-                pv = np;
                 float *Ln = sp + ((z + 1) & 1) * LX;
-                Ln[M + lane] = q[(k + M + 1) % Q];
+                Ln[M + lane] = q[(k + M + 1) % U];
                 if (lane < 2 * M) Ln[hl] = nh;
                 if constexpr (ADJ) {
-                    f[k] = nfq;
-                    gv = ng;
                     float *LFn = sf + ((z + 1) & 1) * LX;
-                    LFn[M + lane] = f[(k + M + 1) % Q];
+                    LFn[M + lane] = f[(k + M + 1) % U];
                     if (lane < 2 * M) LFn[hl] = nfh;
                 }
             }
-            __syncthreads();
-            }
-        }
-    }
+            lds_barrier();
+    };
+    int zb = z0;
+    for (; zb + U < z1; zb += U)
+        static_for<0, U>([&](auto K) __attribute__((always_inline)) {
+            step_row(K, zb + decltype(K)::value, true);
+        });
+    static_for<0, U>([&](auto K) __attribute__((always_inline)) {
+        const int z = zb + decltype(K)::value;
+        if (z < z1) step_row(K, z, z + 1 < z1);
+    });
 }
 
 // 2-D step for grids too small to fill the GPU: one block per tile row of 64
