@@ -276,7 +276,9 @@ enum StepMode { kFwd = 0, kAdj = 1, kAdjPsi = 2, kImage = 3 };
 // Planes a step kernel loads ahead of the one it computes (queue front,
 // kappa', previous level).  Two planes ahead measured no faster on the
 // 304^3 forward: 86.7 against 85.1 us per step with 4 x 4 blocks (211
-// registers), 85.9 with 4 x 2.
+// registers), 85.9 with 4 x 2.  No launch bound caps the registers: one
+// wave per SIMD more spills (4 x 4 forward at 3 waves: 98 against 85 us;
+// fused adjoint at 4 waves: 190 against 171 us).
 template <int M, int MODE>
 constexpr int kLookahead = 1;
 
