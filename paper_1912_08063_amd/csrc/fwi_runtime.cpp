@@ -376,10 +376,16 @@ void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *
         // 3-D: the chunk count is chosen by how well the blocks fill whole
         // waves of resident blocks (occupancy x CUs: a partial last wave idles
         // part of the GPU) against the cost of short chunks (each warms its
-        // z-queue with 2M extra planes of the stencil field, one of the four
-        // streams).  Chunks are at least 4 planes long.  304^3 padded, 8th
-        // order: 8 chunks of 38 planes, 760 blocks for 768 slots; 560 x 560 x
-        // 304: 7 chunks of 44, 2205 blocks (3 % faster than 2 chunks of 152).
+        // z-queue with 2M extra planes of the stencil field before its first
+        // plane).  Scored as (1 + M / zc) x (w + 7/8 (ceil(w) - w)) / w for w
+        // waves: the warm-up weighs twice its share of the bytes (it is also
+        // serial latency), and a partial last wave costs 7/8 of a full one
+        // (its blocks share the bandwidth among fewer).  The weights fit the
+        // measured chunk sweeps at 2 blocks per CU: 304^3 padded, 8th order:
+        // 5 chunks of 61 planes (475 blocks, 84.7 us; 38 planes 101 us, 76
+        // planes 95 us); 560 x 560 x 304: 3 chunks of 102 (forward 1.4 %
+        // faster than 8 of 38); a 128 x 1024 x 1024 slab: 4 chunks of 32
+        // (477 against 502 us with 6 of 22).  Chunks are at least 4 planes.
         static int cus = 0;
         if (cus == 0) {
             int dev = 0;
@@ -397,8 +403,8 @@ void tiles_for(const Geometry &g, int njobs, bool adj, int *ntx, int *nty, int *
             const int zc = (g.nz + n - 1) / n;
             const int nc = (g.nz + zc - 1) / zc;
             const double waves = (double)(per * nc) / (double)slots;
-            const double fill = waves / std::ceil(waves);
-            const double score = (1.0 + 0.5 * M / zc) / fill;
+            const double tail = (waves + 0.875 * (std::ceil(waves) - waves)) / waves;
+            const double score = (1.0 + (double)M / zc) * tail;
             if (n == 1 || score < best - 1e-12) {
                 best = score;
                 z = zc;

@@ -178,9 +178,9 @@ def test_layered_3d_gradient_full_grid_20_steps():
 
 
 def test_salt_3d_full_grid_first_30_steps():
-    """The salt benchmark's grid and launch shape (560 x 560 x 304 padded, 2205
-    forward blocks in 7 z-chunks) against the oracle over its first 30 steps,
-    every trace of the 512 x 512 receiver plane."""
+    """The salt benchmark's grid and launch shape (560 x 560 x 304 padded, 945
+    forward blocks in 3 z-chunks of 102 planes) against the oracle over its
+    first 30 steps, every trace of the 512 x 512 receiver plane."""
     P = f32(wl.salt_3d(nt=30))
     g = gpu_forward(P)
     o = oracle_forward(P)
