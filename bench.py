@@ -92,6 +92,49 @@ def median_time(fn, reps, sync):
     return sorted(times)[len(times) // 2]
 
 
+def tile_march(dev, P, step_us, reps=50):
+    """The forward step's memory pattern without its stencil (fwi_tile_probe):
+    the same 64 x 16 tiles, z-chunks (the step's own choice for this grid),
+    block order and buffer loads, writing 2 cur + kappa prv.  Timed with HIP
+    events bare, with the halo loads, with the LDS staging and barrier, and
+    with the z-chunk warm-up planes as well (the step's whole access pattern),
+    and the bare march and its halo loads with 64-bit loads per lane;
+    `step_frac_of_pattern` is the whole pattern's time over the step's."""
+    import torch
+    from paper_1912_08063_amd import _lib
+    st = torch.cuda.current_stream(dev)
+    nz, ny, nx = (n + 2 * P.nb for n in P.v.shape)
+    fs = fstride_of(P)
+    bufs = [torch.zeros(fs, dtype=torch.float32, device=dev) for _ in range(4)]
+    res = {}
+    for name, mode in (("bare_us", 0), ("halos_us", 1), ("halos_lds_us", 3), ("pattern_us", 7),
+                       ("bare_64bit_us", 8), ("halos_64bit_us", 9)):
+        k = [0]
+
+        def launch():
+            i = k[0]
+            k[0] += 1
+            cur, prv, out = bufs[i % 3], bufs[(i + 1) % 3], bufs[(i + 2) % 3]
+            return _lib.fwi_tile_probe(cur.data_ptr(), prv.data_ptr(), bufs[3].data_ptr(),
+                                       out.data_ptr(), nz, ny, nx, 0, mode, st.cuda_stream)
+        for _ in range(3):
+            zc = launch()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            launch()
+        e1.record(st)
+        torch.cuda.synchronize()
+        res[name] = round(e0.elapsed_time(e1) * 1e3 / reps, 2)
+        res["zc"] = zc
+    del bufs
+    torch.cuda.empty_cache()
+    res["pattern_GBps"] = round(BYTES_PER_UPDATE * P.padded_cells / (res["pattern_us"] * 1e-6) / 1e9, 1)
+    res["step_frac_of_pattern"] = round(res["pattern_us"] / step_us, 4)
+    return res
+
+
 def stream_ceiling(dev, fstride, reps=50):
     """The hand-written 3-read/1-write stream (fwi_stream_probe) over four
     fields of the headline grid's size, rotated like the step's ring: the rate
@@ -562,7 +605,7 @@ def main():
     ap.add_argument("--sections",
                     default="forward,ceiling,c1,forward16,slab,gradient,gradient3d,salt3d,serve",
                     help="comma list of: forward (headline), ceiling (3-read/1-write stream "
-                         "probe), c1 (2-D one-shot latency), forward16 (16th order), slab (one "
+                         "probe and the step's tile-march pattern), c1 (2-D one-shot latency), forward16 (16th order), slab (one "
                          "GPU's z-slab of a 1024^3 model), gradient (2-D, 32 shots), "
                          "gradient3d (headline geometry), salt3d (salt model, revolve), serve "
                          "(request streams)")
@@ -684,6 +727,10 @@ def main():
         ceil["step_frac_of_ceiling"] = round(achieved / ceil["GBps"], 4)
         out["roofline"]["stream_ceiling"] = ceil
         log("stream ceiling: %.1f GB/s (%s)" % (ceil["GBps"], ceil["variant"]))
+        tm = tile_march(dev, P, avg_launch_s * 1e6)
+        out["roofline"]["tile_march"] = tm
+        log("tile march: bare %.1f, halos %.1f, + LDS %.1f, + warm-up %.1f us per launch"
+            % (tm["bare_us"], tm["halos_us"], tm["halos_lds_us"], tm["pattern_us"]))
     if "c1" in sections:
         out["c1"] = c1_section(dev)
     if "gradient" in sections:

@@ -224,6 +224,30 @@ int fwi_stream_probe(const float *a, const float *b, const float *c, float *out,
                      int32_t variant, void *stream);
 
 /*
+ * Diagnostic: the 8th-order forward step's memory pattern with the stencil
+ * taken out, to separate what the pattern costs from what the stencil
+ * costs.  Not part of the method.  The four device fields are laid out as
+ * the 3-D step's (each nz + 8 planes of ny + 8 rows of pitch floats, pitch =
+ * nx + 8 rounded up to a multiple of 64, the 4-cell frame included; fields
+ * 16-byte aligned).  Blocks of 4 wavefronts march 64 x 16 column tiles
+ * through z chunks of zc planes in the step's block order, read cur, prv and
+ * kap once per cell one plane ahead and write out = 2 cur + kap * prv at
+ * the nz x ny x nx cells inside the frame; nothing else is written.  Mode
+ * bits add the step's other work one at a time: 1 the tile's halo rows and
+ * columns of cur, 2 the plane staged in LDS with one barrier per plane, 4
+ * the 4 + 4 planes of cur around each chunk that the step's z-queue reads;
+ * modes 8 and 9 are modes 0 and 1 with 64-bit loads and stores (each lane
+ * two adjacent columns).  The output is the same in every mode for finite
+ * inputs.  zc = 0 takes
+ * the chunk length the forward step picks for this grid; *h_zc (may be
+ * NULL) receives the length used.  Asynchronous on `stream`.  FWI_EINVAL on
+ * a bad argument (NULL field, out equal to an input, a grid dimension out
+ * of 1 .. 2^20, a plane of 2^31 bytes or more, zc < 0, mode outside 0..9).
+ */
+int fwi_tile_probe(const float *cur, const float *prv, const float *kap, float *out, int nz,
+                   int ny, int nx, int zc, int32_t mode, int32_t *h_zc, void *stream);
+
+/*
  * Binomial checkpointing schedule (revolve, Griewank & Walther) for
  * reversing `nsteps` forward steps with `slots` snapshot slots, the initial
  * state being free (it is zero).  Host-only.  Writes up to `cap` actions as

@@ -22,8 +22,9 @@ OP_ADVANCE, OP_TAKESHOT, OP_RESTORE, OP_ADJOINT, OP_RESTART = 1, 2, 3, 4, 5
 
 EXPORTS = ["fwi_strerror", "fwi_last_error", "fwi_cfl_limit", "fwi_workspace_bytes",
            "fwi_forward", "fwi_forward_noalloc", "fwi_gradient", "fwi_forward_ckpt", "fwi_backward",
-           "fwi_revolve_schedule", "fwi_revolve_plan", "fwi_velocity_range", "fwi_stream_probe", "fwi_job_bytes", "fwi_job_create",
-           "fwi_jobs_ws_bytes", "fwi_jobs_advance", "fwi_job_query", "fwi_job_misfit", "fwi_job_misfit_device",
+           "fwi_revolve_schedule", "fwi_revolve_plan", "fwi_velocity_range", "fwi_stream_probe",
+           "fwi_tile_probe", "fwi_job_bytes", "fwi_job_create", "fwi_jobs_ws_bytes",
+           "fwi_jobs_advance", "fwi_job_query", "fwi_job_misfit", "fwi_job_misfit_device",
            "fwi_job_destroy"]
 JOB_FORWARD, JOB_GRADIENT = 0, 1
 
@@ -80,6 +81,7 @@ def load():
     lib.fwi_velocity_range.argtypes = [vp, i64, P(ctypes.c_float), P(ctypes.c_float), vp, u64,
                                        vp]
     lib.fwi_stream_probe.argtypes = [vp, vp, vp, vp, i64, i32, vp]
+    lib.fwi_tile_probe.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, i32, vp, vp]
     lib.fwi_job_bytes.argtypes = [prob, i32, i32, ck, P(u64)]
     lib.fwi_job_create.argtypes = [prob, i32, i32, ck, vp, vp, vp, vp, vp, vp, vp, vp, u64, vp,
                                    P(vp)]
@@ -200,6 +202,14 @@ def fwi_velocity_range(v, n, ws, ws_bytes, stream):
 
 def fwi_stream_probe(a, b, c, out, n, variant, stream):
     _check(load().fwi_stream_probe(a, b, c, out, n, variant, stream), "fwi_stream_probe")
+
+
+def fwi_tile_probe(cur, prv, kap, out, nz, ny, nx, zc, mode, stream):
+    """Returns the z-chunk length used."""
+    h = ctypes.c_int32(0)
+    _check(load().fwi_tile_probe(cur, prv, kap, out, nz, ny, nx, zc, mode, ctypes.byref(h),
+                                 stream), "fwi_tile_probe")
+    return h.value
 
 
 def fwi_job_bytes(prob, kind, chunk, ckpt=None):

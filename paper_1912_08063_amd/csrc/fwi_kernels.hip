@@ -1488,6 +1488,300 @@ void launch_stream_probe(const float *a, const float *b, const float *c, float *
     }
 }
 
+// ------------------------------------------------ tile-march pattern probe
+// The 8th-order forward step's memory pattern with the stencil taken out:
+// blocks of 4 wavefronts x 4 rows march 64 x 16 column tiles through z
+// chunks in the step's block order (XCD-remapped), load cur, prv and kappa
+// once per cell through buffer resources (prv and kappa non-temporal) one
+// plane ahead, and write out = 2 cur + kappa prv with the step's store.
+// Mode bits add the step's other traffic and synchronisation one at a
+// time: 1 the halo rows and columns of cur (loaded one plane ahead, as the
+// step's 16th-order kernels and adjoints do), 2 the plane staged in LDS
+// behind the LDS-only barrier (the written cur value then comes from LDS),
+// 4 the 2M warm-up planes of cur each chunk reads around its own.  Halo and
+// warm-up values enter only a sum scaled by `zero` (0 from the host), so
+// the output stays 2 cur + kappa prv for finite inputs.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_tile_probe(const float *cur, const float *prv,
+                                                    const float *kap, float *out, int nz, int ny,
+                                                    int nx, int pitch, int zc, int ntx, int nty,
+                                                    int ttiles, float zero)
+{
+    constexpr int M = 4, TX = kTileX, RY = 4, NW = 4, TY = RY * NW, NT = 64 * NW;
+    constexpr int LX = TX + 2 * M, LY = TY + 2 * M, LS = LX * LY;
+    constexpr int NYH = (2 * M * TX + NT - 1) / NT, NXH = (TY * 2 * M + NT - 1) / NT;
+    constexpr bool HALO = MODE & 1, LDS = MODE & 2, WARM = MODE & 4;
+    __shared__ float sp[LDS ? 2 * LS : 1];
+    const int tid = threadIdx.x;
+    int b = xcd_remap(blockIdx.x, ttiles);
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty, tz = b / nty;
+    const int z0 = tz * zc, z1 = min(z0 + zc, nz);
+    const int64_t plane = (int64_t)(ny + 2 * M) * pitch;
+    const int pbytes = (int)(plane * (int64_t)sizeof(float));
+    const int lane = tid & 63, wv = tid >> 6;
+    const int col = tx * TX + lane, x = col - M;
+    const int last_row = ny + 2 * M - 1;
+    uint32_t roff[RY], soff[RY];
+    int lrow[RY];
+#pragma unroll
+    for (int i = 0; i < RY; ++i) {
+        const int yy = ty * TY + wv * RY + i;
+        roff[i] = 4u * (uint32_t)(min(yy + M, last_row) * pitch + col);
+        soff[i] = x >= 0 && x < nx && yy < ny ? roff[i] : kDropOffset;
+        lrow[i] = (M + wv * RY + i) * LX + M + lane;
+    }
+    uint32_t hyo[NYH], hxo[NXH];
+    int hyl[NYH], hxl[NXH];
+#pragma unroll
+    for (int q = 0; q < NYH; ++q) {
+        const int h = tid + NT * q;
+        const int r = (h / TX) % (2 * M), c = h % TX;
+        const int ly = r < M ? r : r + TY;
+        const int yg = ty * TY - M + ly;
+        hyo[q] = 4u * (uint32_t)(min(max(yg + M, 0), last_row) * pitch + tx * TX + c);
+        hyl[q] = h < 2 * M * TX ? ly * LX + M + c : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < NXH; ++q) {
+        const int h = tid + NT * q;
+        const int r = (h / (2 * M)) % TY, c = h % (2 * M);
+        const int lc = c < M ? c : c + TX;
+        const int cm = min(max(tx * TX - M + lc, 0), pitch - 1);
+        hxo[q] = 4u * (uint32_t)(min(ty * TY + r + M, last_row) * pitch + cm);
+        hxl[q] = h < TY * 2 * M ? (M + r) * LX + lc : -1;
+    }
+    float acc = 0.f;
+    if constexpr (WARM) {
+        // memory planes z0 .. z0+M-1 and z1+M .. z1+2M-1: the M planes on
+        // either side of the chunk that the step's z-queue reads
+#pragma unroll
+        for (int s = 0; s < 2 * M; ++s) {
+            const int zm = s < M ? z0 + s : z1 + s;
+            const rsrc_t pw = plane_rsrc(gptr(cur), zm, plane, pbytes);
+#pragma unroll
+            for (int i = 0; i < RY; ++i) acc += ldb(pw, roff[i]);
+        }
+    }
+    // Three-slot rings, chunk plane j in slot j % 3: cur and its halos are
+    // loaded two planes ahead, so the plane staged into LDS at the end of an
+    // iteration was loaded one iteration earlier (as the step's queue front
+    // and halo ring are); kappa and prv one plane ahead.
+    float q[3][RY], kv[3][RY], pv[3][RY];
+    float hy[3][HALO ? NYH : 1], hx[3][HALO ? NXH : 1];
+    auto load_cur = [&](const int sl, const int z) __attribute__((always_inline)) {
+        const rsrc_t pc = plane_rsrc(gptr(cur), z + M, plane, pbytes);
+        if constexpr (HALO) {
+#pragma unroll
+            for (int h = 0; h < NYH; ++h) hy[sl][h] = ldb(pc, hyo[h]);
+#pragma unroll
+            for (int h = 0; h < NXH; ++h) hx[sl][h] = ldb(pc, hxo[h]);
+        }
+#pragma unroll
+        for (int i = 0; i < RY; ++i) q[sl][i] = ldb(pc, roff[i]);
+    };
+    auto load_pw = [&](const int sl, const int z) __attribute__((always_inline)) {
+        const rsrc_t pk = plane_rsrc(gptr(kap), z + M, plane, pbytes);
+        const rsrc_t pp = plane_rsrc(gptr(prv), z + M, plane, pbytes);
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            kv[sl][i] = ldb_stream(pk, roff[i]);
+            pv[sl][i] = ldb_stream(pp, roff[i]);
+        }
+    };
+    // plane z's cells (and halos) into LDS buffer z & 1, or its halos into
+    // the sum
+    auto stage = [&](const int sl, const int z) __attribute__((always_inline)) {
+        if constexpr (LDS) {
+            float *L = sp + (z & 1) * LS;
+#pragma unroll
+            for (int i = 0; i < RY; ++i) L[lrow[i]] = q[sl][i];
+            if constexpr (HALO) {
+#pragma unroll
+                for (int h = 0; h < NYH; ++h)
+                    if (hyl[h] >= 0) L[hyl[h]] = hy[sl][h];
+#pragma unroll
+                for (int h = 0; h < NXH; ++h)
+                    if (hxl[h] >= 0) L[hxl[h]] = hx[sl][h];
+            }
+        } else if constexpr (HALO) {
+#pragma unroll
+            for (int h = 0; h < NYH; ++h) acc += hy[sl][h];
+#pragma unroll
+            for (int h = 0; h < NXH; ++h) acc += hx[sl][h];
+        }
+    };
+    load_cur(0, z0);
+    if (z0 + 1 < z1) load_cur(1, z0 + 1);
+    load_pw(0, z0);
+    stage(0, z0);
+    if constexpr (LDS) lds_barrier();
+    // plane z (chunk slot K): loads of z+2 (cur) and z+1 (kappa, prv), the
+    // store of z, then plane z+1 staged
+    auto step_plane = [&](auto K, const int z, const bool more1, const bool more2)
+        __attribute__((always_inline)) {
+        constexpr int c = decltype(K)::value, c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        if (more2) load_cur(c2, z + 2);
+        if (more1) load_pw(c1, z + 1);
+        const rsrc_t po = plane_rsrc(gptr(out), z + M, plane, pbytes);
+        const float extra = zero * acc;
+        const float *L = sp + (z & 1) * LS;
+#pragma unroll
+        for (int i = 0; i < RY; ++i) {
+            const float cv = LDS ? L[lrow[i]] : q[c][i];
+            stb_stream(po, soff[i], fmaf(kv[c][i], pv[c][i], 2.f * cv) + extra);
+        }
+        if (more1) stage(c1, z + 1);
+        if constexpr (LDS) lds_barrier();
+    };
+    int z = z0;
+    for (; z + 5 <= z1; z += 3) {
+        step_plane(Int<0>{}, z, true, true);
+        step_plane(Int<1>{}, z + 1, true, true);
+        step_plane(Int<2>{}, z + 2, true, true);
+    }
+    static_for<0, 4>([&](auto K) __attribute__((always_inline)) {
+        const int zz = z + decltype(K)::value;
+        if (zz < z1) step_plane(Int<decltype(K)::value % 3>{}, zz, zz + 1 < z1, zz + 2 < z1);
+    });
+}
+
+// The bare march (with or without the halo loads) with 64-bit loads and
+// stores: each lane owns two adjacent columns of two rows, so one wavefront
+// instruction covers two 256-byte row segments.  Same tiles, chunks, block
+// order and output as k_tile_probe; halo values enter the zero-scaled sum.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <bool HALO>
+__global__ __launch_bounds__(256) void k_tile_probe64(const float *cur, const float *prv,
+                                                      const float *kap, float *out, int nz,
+                                                      int ny, int nx, int pitch, int zc, int ntx,
+                                                      int nty, int ttiles, float zero)
+{
+    constexpr int M = 4, TX = kTileX, TY = 16;
+    const int tid = threadIdx.x;
+    int b = xcd_remap(blockIdx.x, ttiles);
+    const int tx = b % ntx;
+    b /= ntx;
+    const int ty = b % nty, tz = b / nty;
+    const int z0 = tz * zc, z1 = min(z0 + zc, nz);
+    const int64_t plane = (int64_t)(ny + 2 * M) * pitch;
+    const int pbytes = (int)(plane * (int64_t)sizeof(float));
+    const int lane = tid & 63, wv = tid >> 6;
+    const int col = tx * TX + 2 * (lane & 31);   // even: 8-byte aligned
+    const int last_row = ny + 2 * M - 1;
+    uint32_t roff[2], soff[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int yy = ty * TY + wv * 4 + (lane >> 5) + 2 * i;
+        roff[i] = 4u * (uint32_t)(min(yy + M, last_row) * pitch + col);
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int x = col + e - M;
+            soff[i][e] = x >= 0 && x < nx && yy < ny ? roff[i] + 4u * e : kDropOffset;
+        }
+    }
+    // halos: 8 rows of 64 columns (one pair per thread) and 16 rows of 4 + 4
+    // columns (two pairs per row, threads 0..63)
+    uint32_t hyo, hxo;
+    {
+        const int r = tid >> 5, c = 2 * (tid & 31);
+        const int ly = r < M ? r : r + TY;
+        hyo = 4u * (uint32_t)(min(ty * TY - M + ly + M, last_row) * pitch + tx * TX + c);
+        const int xr = (tid >> 2) & 15, xp = tid & 3;
+        const int xc = min(max(tx * TX - M + (xp < 2 ? 2 * xp : TX + 2 * xp), 0), pitch - 2);
+        hxo = 4u * (uint32_t)(min(ty * TY + xr + M, last_row) * pitch + xc);
+    }
+    auto ld2 = [&](rsrc_t r, uint32_t off) __attribute__((always_inline)) {
+        return __builtin_bit_cast(vf2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+    };
+    auto ld2_stream = [&](rsrc_t r, uint32_t off) __attribute__((always_inline)) {
+        return __builtin_bit_cast(vf2,
+                                  __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, kCacheNT));
+    };
+    float acc = 0.f;
+    vf2 q[2][2], kv[2][2], pv[2][2], hh[2][2];
+    auto load = [&](const int sl, const int z) __attribute__((always_inline)) {
+        const rsrc_t pc = plane_rsrc(gptr(cur), z + M, plane, pbytes);
+        const rsrc_t pk = plane_rsrc(gptr(kap), z + M, plane, pbytes);
+        const rsrc_t pp = plane_rsrc(gptr(prv), z + M, plane, pbytes);
+        if constexpr (HALO) {
+            hh[sl][0] = ld2(pc, hyo);
+            hh[sl][1] = ld2(pc, hxo);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            q[sl][i] = ld2(pc, roff[i]);
+            kv[sl][i] = ld2_stream(pk, roff[i]);
+            pv[sl][i] = ld2_stream(pp, roff[i]);
+        }
+    };
+    load(0, z0);
+    auto step_plane = [&](auto K, const int z, const bool more) __attribute__((always_inline)) {
+        constexpr int c = decltype(K)::value, cn = 1 - c;
+        if (more) load(cn, z + 1);
+        if constexpr (HALO) acc += hh[c][0].x + hh[c][0].y + hh[c][1].x + hh[c][1].y;
+        const rsrc_t po = plane_rsrc(gptr(out), z + M, plane, pbytes);
+        const float extra = zero * acc;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const vf2 o = {fmaf(kv[c][i].x, pv[c][i].x, 2.f * q[c][i].x) + extra,
+                           fmaf(kv[c][i].y, pv[c][i].y, 2.f * q[c][i].y) + extra};
+            if (soff[i][0] != kDropOffset && soff[i][1] != kDropOffset)
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, o), po,
+                                                      (int)roff[i], 0, kCacheNT);
+            else {
+                stb_stream(po, soff[i][0], o.x);
+                stb_stream(po, soff[i][1], o.y);
+            }
+        }
+    };
+    int z = z0;
+    for (; z + 2 < z1; z += 2) {
+        step_plane(Int<0>{}, z, true);
+        step_plane(Int<1>{}, z + 1, true);
+    }
+    static_for<0, 2>([&](auto K) __attribute__((always_inline)) {
+        const int zz = z + decltype(K)::value;
+        if (zz < z1) step_plane(K, zz, zz + 1 < z1);
+    });
+}
+
+// One launch of the tile-march probe over nz x ny x nx cells (8th-order
+// frame, rows of `pitch` floats) in z chunks of zc planes.
+void launch_tile_probe(const float *cur, const float *prv, const float *kap, float *out, int nz,
+                       int ny, int nx, int pitch, int zc, int mode, hipStream_t st)
+{
+    const int ntx = (nx + 4 + kTileX - 1) / kTileX, nty = (ny + 15) / 16;
+    const int nzc = (nz + zc - 1) / zc;
+    const int T = ntx * nty * nzc;
+    if (mode & 8) {
+        if (mode & 1)
+            hipLaunchKernelGGL(k_tile_probe64<true>, dim3(T), dim3(256), 0, st, cur, prv, kap,
+                               out, nz, ny, nx, pitch, zc, ntx, nty, T, 0.f);
+        else
+            hipLaunchKernelGGL(k_tile_probe64<false>, dim3(T), dim3(256), 0, st, cur, prv, kap,
+                               out, nz, ny, nx, pitch, zc, ntx, nty, T, 0.f);
+        return;
+    }
+    switch (mode & 7) {
+#define FWI_TILE_PROBE(m)                                                                     \
+    case m:                                                                                   \
+        hipLaunchKernelGGL(k_tile_probe<m>, dim3(T), dim3(256), 0, st, cur, prv, kap, out, nz, \
+                           ny, nx, pitch, zc, ntx, nty, T, 0.f);                              \
+        break;
+        FWI_TILE_PROBE(0)
+        FWI_TILE_PROBE(1)
+        FWI_TILE_PROBE(2)
+        FWI_TILE_PROBE(3)
+        FWI_TILE_PROBE(4)
+        FWI_TILE_PROBE(5)
+        FWI_TILE_PROBE(6)
+        FWI_TILE_PROBE(7)
+#undef FWI_TILE_PROBE
+    }
+}
+
 // Launch tables of a serving chunk (see AssembleArgs): block i copies entry
 // i from the job's memory and patches its time window and level list; block
 // 0 also writes the launch's slices of the prefix arrays and level lists.

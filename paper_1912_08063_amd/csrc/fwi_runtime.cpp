@@ -56,6 +56,8 @@ void launch_step2d_multi(int M, const Job *jobs, int njobs, int tiles_per_job, i
 int scratch_address(void **ptr);
 void launch_stream_probe(const float *a, const float *b, const float *c, float *o, int64_t n,
                          int variant, hipStream_t st);
+void launch_tile_probe(const float *cur, const float *prv, const float *kap, float *out, int nz,
+                       int ny, int nx, int pitch, int zc, int mode, hipStream_t st);
 }  // namespace fwi
 
 using namespace fwi;
@@ -1444,6 +1446,39 @@ int fwi_stream_probe(const float *a, const float *b, const float *c, float *out,
                          reinterpret_cast<uintptr_t>(c) | reinterpret_cast<uintptr_t>(out);
     if (al & 15) return fail(FWI_EINVAL, "arrays must be 16-byte aligned");
     launch_stream_probe(a, b, c, out, n, variant, static_cast<hipStream_t>(stream));
+    HIP_TRY(hipGetLastError());
+    return FWI_OK;
+}
+
+int fwi_tile_probe(const float *cur, const float *prv, const float *kap, float *out, int nz,
+                   int ny, int nx, int zc, int32_t mode, int32_t *h_zc, void *stream)
+{
+    if (!cur || !prv || !kap || !out) return fail(FWI_EINVAL, "NULL field");
+    if (out == cur || out == prv || out == kap) return fail(FWI_EINVAL, "out must be distinct");
+    if (nz < 1 || ny < 1 || nx < 1 || nz > (1 << 20) || ny > (1 << 20) || nx > (1 << 20))
+        return fail(FWI_EINVAL, "grid %d x %d x %d out of range", nz, ny, nx);
+    if (zc < 0) return fail(FWI_EINVAL, "zc must be >= 0");
+    if (mode < 0 || mode > 9) return fail(FWI_EINVAL, "mode must be 0..9");
+    Geometry g;
+    g.ndim = 3;
+    g.M = 4;
+    g.gy = 4;
+    g.nz = nz;
+    g.ny = ny;
+    g.nx = nx;
+    g.pitch = (int)align_up((uint64_t)nx + 8, 64);
+    g.nya = ny + 8;
+    g.plane = (int64_t)g.nya * g.pitch;
+    if (g.plane * (int64_t)sizeof(float) >= (int64_t(1) << 31))
+        return fail(FWI_EINVAL, "plane too large for 32-bit offsets");
+    if (zc == 0) {
+        int ntx = 0, nty = 0, nzc = 0;
+        tiles_for(g, 1, false, &ntx, &nty, &nzc, &zc);
+    }
+    zc = std::min(zc, nz);
+    if (h_zc) *h_zc = zc;
+    launch_tile_probe(cur, prv, kap, out, nz, ny, nx, g.pitch, zc, mode,
+                      static_cast<hipStream_t>(stream));
     HIP_TRY(hipGetLastError());
     return FWI_OK;
 }

@@ -72,6 +72,24 @@ def test_invalid_problems_rejected_before_any_device_call(bad):
     assert st == _lib.FWI_EINVAL
 
 
+def test_tile_probe_rejects_bad_arguments_before_any_device_call():
+    lib = _lib.load()
+    a, b, c, o = (ctypes.c_void_p(x) for x in (0x1000, 0x2000, 0x3000, 0x4000))
+    zc = ctypes.c_int32(-1)
+    bad = [
+        (None, b, c, o, 8, 8, 8, 0, 0),      # NULL field
+        (a, b, c, a, 8, 8, 8, 0, 0),         # out equal to an input
+        (a, b, c, o, 0, 8, 8, 0, 0),         # empty grid
+        (a, b, c, o, 8, 8, 1 << 21, 0, 0),   # dimension out of range
+        (a, b, c, o, 8, 1 << 20, 1 << 20, 0, 0),  # plane of 2^31 bytes or more
+        (a, b, c, o, 8, 8, 8, -1, 0),        # negative chunk length
+        (a, b, c, o, 8, 8, 8, 0, 10),        # unknown mode
+    ]
+    for args in bad:
+        assert lib.fwi_tile_probe(*args, ctypes.byref(zc), None) == _lib.FWI_EINVAL, args
+    assert zc.value == -1
+
+
 def test_workspace_too_small_is_enomem_without_device():
     p = _prob()
     lib = _lib.load()
