@@ -2041,6 +2041,42 @@ void launch_prep_kappa(const float *v, float *kappa, int M, int gy, int nz, int 
                        kappa, M, gy, nz, ny, nx, pitch, nya, nb, nzm, nym, nxm, total, dt_dx);
 }
 
+// Zero the frame and row padding of nf consecutive fields (fstride floats
+// each: nzp planes of nya rows of pitch floats; grid cells are planes
+// M .. M+nz-1, rows gy .. gy+ny-1, columns M .. M+nx-1).  One wavefront per
+// row: frame rows are cleared whole, grid rows outside columns M .. M+nx-1.
+__global__ __launch_bounds__(256) void k_zero_frames(float *__restrict__ f, int64_t nrows,
+                                                     int64_t fstride, int nya, int pitch, int M,
+                                                     int gy, int nz, int ny, int nx)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int planes = (int)(fstride / ((int64_t)nya * pitch));
+    for (int64_t r = w0; r < nrows; r += nw) {
+        const int64_t fld = r / ((int64_t)planes * nya);
+        const int rem = (int)(r - fld * planes * nya);
+        const int z = rem / nya, y = rem - (rem / nya) * nya;
+        float *row = f + fld * fstride + ((int64_t)z * nya + y) * pitch;
+        const bool frame = z < M || z >= nz + M || y < gy || y >= ny + gy;
+        if (frame) {
+            float4 *row4 = reinterpret_cast<float4 *>(row);
+            for (int c = lane; c < pitch / 4; c += 64) row4[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            if (lane < M) row[lane] = 0.f;
+            for (int c = nx + M + lane; c < pitch; c += 64) row[c] = 0.f;
+        }
+    }
+}
+
+void launch_zero_frames(float *p, int64_t nfields, int64_t fstride, int nya, int pitch, int M,
+                        int gy, int nz, int ny, int nx, hipStream_t st)
+{
+    const int64_t nrows = nfields * (fstride / pitch);
+    hipLaunchKernelGGL(k_zero_frames, dim3(grid_for(nrows * 64, 256, 8192)), dim3(256), 0, st, p,
+                       nrows, fstride, nya, pitch, M, gy, nz, ny, nx);
+}
+
 void launch_fill(float *p, int64_t n, float val, hipStream_t st)
 {
     // n is a multiple of 4 (fields are multiples of 64 floats)

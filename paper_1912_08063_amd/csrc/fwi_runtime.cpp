@@ -31,6 +31,8 @@ void launch_prep_kappa(const float *v, float *kappa, int M, int gy, int nz, int 
                        int pitch, int nya, int nb, int nzm, int nym, int nxm, int64_t total,
                        float dt_dx, hipStream_t st);
 void launch_fill(float *p, int64_t n, float val, hipStream_t st);
+void launch_zero_frames(float *p, int64_t nfields, int64_t fstride, int nya, int pitch, int M,
+                        int gy, int nz, int ny, int nx, hipStream_t st);
 void launch_snapshot(const Job *jobs, int njobs, int64_t fstride, int slot, int time, int dir,
                      int mask, const LevelMap &lm, hipStream_t st);
 void launch_gather(const Job *jobs, const int *gprefix, int njobs, int gblocks, int threads,
@@ -891,12 +893,28 @@ int rv_to_ring(Ctx &c, Held &h, int L)
 
 void zero(float *p, uint64_t floats, hipStream_t st) { launch_fill(p, (int64_t)floats, 0.f, st); }
 
+// Frames and row padding of nf consecutive fields.  Step kernels never store
+// there and read it as the zero boundary; grid cells of a level are all
+// written by the step that produces it before anything reads them, so a
+// level store needs only its frames cleared (and the initial levels 0 and -1
+// cleared whole).  For a checkpoint ring kept whole in HBM this is ~10 % of
+// the bytes of a full clear.
+void zero_frames(const Ctx &c, float *p, uint64_t nf)
+{
+    const Geometry &g = c.g;
+    launch_zero_frames(p, (int64_t)nf, g.fstride, g.nya, g.pitch, g.M, g.gy, g.nz, g.ny, g.nx,
+                       c.st);
+}
+
 // Forward sweep 0 -> nt recording traces and taking the policy's snapshots.
 int forward_phase(Ctx &c, bool record)
 {
     const int nt = c.p->nt;
     const uint64_t fs = (uint64_t)c.g.fstride;
-    if (!c.plan) zero(c.jobs[0].ring, fs * c.po.R * c.p->nshots, c.st);
+    if (!c.plan) {
+        zero_frames(c, c.jobs[0].ring, (uint64_t)c.po.R * c.p->nshots);
+        TRY(snapshot(c, 0, 0, 2));   // levels 0 and -1: the zero initial state
+    }
     if (c.po.kind == FWI_CKPT_REVOLVE) {
         int64_t steps = 0;
         std::vector<Action> acts = revolve_schedule(nt, c.po.nsnap, &steps);
@@ -904,7 +922,7 @@ int forward_phase(Ctx &c, bool record)
         // steps store only grid cells, so fields they write must start with
         // a zero frame: the snapshot store is cleared once
         if (!revolve_copies() && c.po.nsnap > 0 && !c.plan)
-            zero(c.jobs[0].snap, 2 * fs * c.po.nsnap * c.p->nshots, c.st);
+            zero_frames(c, c.jobs[0].snap, 2 * (uint64_t)c.po.nsnap * c.p->nshots);
         int cur = 0;
         Held h;
         for (size_t i = 0; i < acts.size() && acts[i].op != OP_ADJOINT; ++i) {
@@ -1590,7 +1608,11 @@ int fwi_job_create(const fwi_problem *prob, int32_t kind, int32_t chunk, const f
         st = stage(c, v, src, src_pos, rec_pos, rec ? J->rec : nullptr, J->res,
                    kind == FWI_JOB_GRADIENT);
         if (st) return st;
-        zero(c.jobs[0].ring, (uint64_t)c.g.fstride * c.po.R, c.st);
+        // frames of every level; levels 0 and -1 whole (the job's program
+        // also clears them before its first step)
+        zero_frames(c, c.jobs[0].ring, (uint64_t)c.po.R);
+        zero(c.jobs[0].ring, (uint64_t)c.g.fstride, c.st);
+        zero(c.jobs[0].ring + (uint64_t)c.g.fstride * (c.po.R - 1), (uint64_t)c.g.fstride, c.st);
         HIP_TRY(hipGetLastError());
         J->rounds = kind == FWI_JOB_GRADIENT && c.po.kind == FWI_CKPT_REVOLVE;
         build_program(J.get());
